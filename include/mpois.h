@@ -1,0 +1,159 @@
+/*
+ * mpois -- fast direct Poisson solver for MI355X (gfx950), C ABI.
+ *
+ * Solves the discrete Poisson equation  Lap(phi) = g  (Eq. 1 of the paper, in
+ * 1, 2 or 3 dimensions) on a uniform box by the three-step method of
+ * Section 2.1: forward transforms of Table 2 along every axis, division of
+ * every coefficient by the sum of the per-axis eigenvalues (Section 2.3, from
+ * Table 3 for the pseudo-spectral approximation or Table 4 for second-order
+ * finite differences), and the backward transforms.
+ *
+ * Conventions common to all calls
+ *  - Every function returns an mpois_status; 0 (MPOIS_OK) is success.  Output
+ *    parameters are written only on success.
+ *  - Arrays are C-contiguous, shape (n[0][, n[1][, n[2]]]), the last axis
+ *    contiguous.  rhs and phi are device pointers owned by the caller.
+ *  - Element type: double for MPOIS_F64 and MPOIS_F32_REFINE, float for
+ *    MPOIS_F32.
+ *  - Streams are passed as `void*` holding a hipStream_t (NULL = the default
+ *    stream).  Execution is asynchronous on that stream; nothing is allocated
+ *    and the host is not synchronised by mpois_execute / mpois_execute_batch.
+ *  - A plan may be used by one stream at a time; distinct plans are
+ *    independent.
+ */
+#ifndef MPOIS_H
+#define MPOIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPOIS_OK = 0,
+  MPOIS_ERR_INVALID = 1,        /* bad argument (shape, spacing, pointer, aliasing) */
+  MPOIS_ERR_UNSUPPORTED = 2,    /* valid request this library does not implement */
+  MPOIS_ERR_NOMEM = 3,          /* device allocation failed */
+  MPOIS_ERR_DEVICE = 4,         /* no usable GPU, or a HIP call failed */
+  MPOIS_ERR_NOT_CONVERGED = 5,  /* refinement ended above rtol (phi holds the last iterate) */
+  MPOIS_ERR_NONFINITE = 6       /* the residual norm is NaN or infinite */
+} mpois_status;
+
+/* Boundary condition of one face (the same on both faces of an axis). */
+typedef enum { MPOIS_PERIODIC = 0, MPOIS_DIRICHLET = 1, MPOIS_NEUMANN = 2 } mpois_bc;
+
+/* Grid of Section 2.1: vertex = the paper's "regular" grid (Dirichlet: interior
+ * nodes x_j=(j+1)L/(n+1); Neumann: boundary nodes included, x_j=jL/(n-1));
+ * staggered: x_j=(j+1/2)L/n.  Ignored on periodic axes (x_j=jL/n). */
+typedef enum { MPOIS_VERTEX = 0, MPOIS_STAGGERED = 1 } mpois_grid;
+
+/* Eigenvalues of Table 3 (pseudo-spectral) or Table 4 (2nd-order differences). */
+typedef enum { MPOIS_SPECTRAL = 0, MPOIS_FD2 = 1 } mpois_approx;
+
+/* Working precision: FP64; FP32; FP32 transforms with FP64 residual refinement
+ * (finite differences only). */
+typedef enum { MPOIS_F64 = 0, MPOIS_F32 = 1, MPOIS_F32_REFINE = 2 } mpois_prec;
+
+/* Plan flags. */
+#define MPOIS_FLAG_GRAPH 1u   /* capture the launch sequence once per (rhs, phi) pair and replay it */
+#define MPOIS_FLAG_TUNE 2u    /* time the candidate kernel shapes at plan creation and keep the fastest */
+#define MPOIS_FLAG_PROFILE 4u /* record an event after every launch of an execute (not captured) */
+
+/* One grid.  ndim in 1..3; n[d] >= 1 (>= 2 on vertex Neumann axes); h[d] > 0
+ * finite; bc[d][0] and bc[d][1] are the two faces of axis d and must be equal
+ * (periodic must be on both).  Entries beyond ndim are ignored. */
+typedef struct {
+  int ndim;
+  int64_t n[3];
+  double h[3];
+  int bc[3][2];   /* mpois_bc */
+  int grid[3];    /* mpois_grid */
+} mpois_grid_desc;
+
+typedef struct mpois_plan_s* mpois_plan;
+
+typedef struct {
+  int iters;             /* FP32 solves performed by the last execute (1 + corrections) */
+  double rel_resid;      /* ||g_c - L_h phi|| / ||g_c|| of the last result (FD plans; NaN otherwise) */
+  double zero_mode_rhs;  /* weighted mean of g removed by the solve (0 when nonsingular) */
+} mpois_info;
+
+/* Build a plan for one grid (Sections 2.1-2.3, Tables 2-4).
+ * approx: mpois_approx; prec: mpois_prec.  For MPOIS_F32_REFINE, max_iter is
+ * the fixed number of FP64-residual corrections run by every execute (>= 1)
+ * and rtol (>= 0; 0 disables the check) is compared with the relative residual
+ * by mpois_get_info; both are ignored for the other precisions.
+ * Allocates the plan's workspace and device tables on the current device.
+ * Errors: INVALID (bad descriptor), UNSUPPORTED (different conditions on the
+ * two faces of one axis; spectral with refinement), DEVICE (no GPU), NOMEM. */
+mpois_status mpois_plan_create(const mpois_grid_desc* grid, int approx, int prec, double rtol,
+                               int max_iter, unsigned flags, mpois_plan* out);
+
+/* Build one plan for `count` independent grids of the same ndim (1..2048),
+ * solved together by mpois_execute_batch.  Same rules as mpois_plan_create
+ * for every entry. */
+mpois_status mpois_plan_create_batch(const mpois_grid_desc* grids, int count, int approx, int prec,
+                                     double rtol, int max_iter, unsigned flags, mpois_plan* out);
+
+/* Solve for one right-hand side: phi = Lap^{-1} rhs.  rhs is read-only;
+ * rhs == phi (in place) is allowed except with MPOIS_F32_REFINE, which needs
+ * rhs for the residual; partial overlap is INVALID.  When every axis is
+ * periodic or Neumann the zero mode is set to zero: phi solves for g minus
+ * its weighted mean (weights 1/2 on the end nodes of vertex Neumann axes, 1
+ * elsewhere) and has zero weighted mean. */
+mpois_status mpois_execute(mpois_plan plan, const void* rhs, void* phi, void* stream);
+
+/* Solve every grid of a batch plan: rhs[i], phi[i] are the device arrays of
+ * grid i (host arrays of `count` device pointers). */
+mpois_status mpois_execute_batch(mpois_plan plan, const void* const* rhs, void* const* phi, void* stream);
+
+/* Residual report of the last execute (single-grid plans; for batch plans the
+ * worst grid).  Synchronises `stream`.  Returns NOT_CONVERGED when rtol > 0 and
+ * rel_resid > rtol, NONFINITE when the residual is not finite; *out is written
+ * in both cases. */
+mpois_status mpois_get_info(mpois_plan plan, void* stream, mpois_info* out);
+
+/* Free the plan and everything it owns.  NULL is a no-op. */
+mpois_status mpois_destroy(mpois_plan plan);
+
+/* Device bytes owned by the plan (workspace and tables); 0 for NULL. */
+size_t mpois_workspace_bytes(mpois_plan plan);
+
+/* Per-launch timing of the last execute of a plan created with
+ * MPOIS_FLAG_PROFILE: for launch i, ms[i] is the time between the end of the
+ * previous launch (or the start of the execute) and its end, measured with HIP
+ * events on the execute's stream; bytes[i] its algorithmic HBM bytes (each
+ * input element read once, each output written once); kernel[i] the
+ * line-transform kernel shape, 100 for the residual, 101 for the reduction.
+ * Writes min(cap, *count) entries; *count receives the number of launches.
+ * Synchronises `stream`. */
+mpois_status mpois_profile(mpois_plan plan, void* stream, int cap, double* ms, double* bytes, int* kernel,
+                           int* count);
+
+/* Static text for a status code. */
+const char* mpois_status_string(mpois_status s);
+
+/* Host-only helpers (no device needed). -------------------------------------- */
+
+/* Check a descriptor as mpois_plan_create would, without touching the device. */
+mpois_status mpois_validate(const mpois_grid_desc* grid, int approx, int prec, int max_iter);
+
+/* lambda_k, k = 0..n-1, of one axis as used by the solver (Table 3 or 4,
+ * unscaled, FP64), written to out[0..n-1]. */
+mpois_status mpois_axis_eigenvalues(int bc, int grid, int approx, int64_t n, double h, double* out);
+
+/* How one axis is transformed: forward/backward line-transform kinds (0 real
+ * DFT to half-complex, 1 its inverse, 2 DCT-II, 3 DCT-III, 4 DST-II, 5 DST-III,
+ * 6 DCT-I, 7 DST-I), complex DFT length M, work length P (P > M means a
+ * Bluestein convolution), and the radices of the Stockham stages (up to
+ * `cap`; *nradix receives the count). */
+mpois_status mpois_axis_plan(int bc, int grid, int64_t n, int* kind_fwd, int* kind_bwd, int* M, int* P,
+                             int* radices, int cap, int* nradix);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPOIS_H */

@@ -1,0 +1,142 @@
+// Auxiliary kernels: FP64 stencil residual with the zero-mode reductions, the
+// fixed-order finalisation of block partial sums, and a zero fill.
+//
+// resid_kernel computes g - m_g - L_h phi for the second-order stencil of
+// Eq. (FD2) with the boundary closure of each axis, and block partial sums of
+// w phi, w g, r^2 and (g - m_g)^2, where w is the gauge / compatibility weight
+// (1/2 on the end nodes of vertex-grid Neumann axes, 1 elsewhere).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mpois {
+
+// ----------------------------------------------------------------------------- residual
+__device__ __forceinline__ double axis_weight(int clo, int64_t i, int64_t n) {
+  return (clo == C_NV && (i == 0 || i == n - 1)) ? 0.5 : 1.0;
+}
+
+// Second difference along one axis at index i (stride s) with the closure of that axis.
+__device__ __forceinline__ double second_diff(const double* __restrict__ phi, int64_t idx, int64_t i,
+                                              int64_t n, int64_t s, int clo, double c) {
+  if (clo == C_NONE) return 0.0;
+  double lo, hi;
+  if (i > 0) lo = phi[idx - s];
+  else {
+    switch (clo) {
+      case C_PER: lo = phi[idx + (n - 1) * s]; break;
+      case C_DV: lo = 0.0; break;
+      case C_DS: lo = -c; break;
+      case C_NV: lo = phi[idx + s]; break;
+      default: lo = c; break;  // C_NS
+    }
+  }
+  if (i < n - 1) hi = phi[idx + s];
+  else {
+    switch (clo) {
+      case C_PER: hi = phi[idx - (n - 1) * s]; break;
+      case C_DV: hi = 0.0; break;
+      case C_DS: hi = -c; break;
+      case C_NV: hi = phi[idx - s]; break;
+      default: hi = c; break;
+    }
+  }
+  return lo - 2.0 * c + hi;
+}
+
+constexpr int RESID_NT = 256;
+
+__global__ void __launch_bounds__(RESID_NT) resid_kernel(ResidArgs a) {
+  const int64_t n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  const int64_t rows = n0 * n1;
+  const double mg = a.mg ? a.mg[0] : 0.0;
+  double s_wphi = 0.0, s_wg = 0.0, s_r2 = 0.0, s_g2 = 0.0;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int64_t i0 = row / n1, i1 = row - i0 * n1;
+    const double w01 = axis_weight(a.clo[0], i0, n0) * axis_weight(a.clo[1], i1, n1);
+    for (int64_t i2 = threadIdx.x; i2 < n2; i2 += RESID_NT) {
+      const int64_t idx = row * n2 + i2;
+      const double c = a.phi[idx];
+      const double gv = a.g[idx];
+      const double lap = a.inv_h2[2] * second_diff(a.phi, idx, i2, n2, 1, a.clo[2], c) +
+                         a.inv_h2[1] * second_diff(a.phi, idx, i1, n1, n2, a.clo[1], c) +
+                         a.inv_h2[0] * second_diff(a.phi, idx, i0, n0, n1 * n2, a.clo[0], c);
+      const double gc = gv - mg;
+      const double r = gc - lap;
+      if (a.r) {
+        if (a.r_f64) static_cast<double*>(a.r)[idx] = r;
+        else static_cast<float*>(a.r)[idx] = float(r);
+      }
+      const double w = w01 * axis_weight(a.clo[2], i2, n2);
+      s_wphi += w * c;
+      s_wg += w * gv;
+      s_r2 += r * r;
+      s_g2 += gc * gc;
+    }
+  }
+  __shared__ double red[4][RESID_NT];
+  red[0][threadIdx.x] = s_wphi;
+  red[1][threadIdx.x] = s_wg;
+  red[2][threadIdx.x] = s_r2;
+  red[3][threadIdx.x] = s_g2;
+  __syncthreads();
+  for (int off = RESID_NT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) a.partials[int64_t(blockIdx.x) * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Sum the block partials in a fixed order; derive the gauge shift and the mean of g.
+__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ partials, int nblocks,
+                                                       double inv_wsum, double* __restrict__ scalars) {
+  __shared__ double red[4][256];
+  double s[4] = {0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += 256)
+    for (int q = 0; q < 4; ++q) s[q] += partials[int64_t(b) * 4 + q];
+  for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = s[q];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    scalars[S_WPHI] = red[0][0];
+    scalars[S_WG] = red[1][0];
+    scalars[S_R2] = red[2][0];
+    scalars[S_G2] = red[3][0];
+    scalars[S_SHIFT] = red[0][0] * inv_wsum;
+    scalars[S_MG] = red[1][0] * inv_wsum;
+  }
+}
+
+// Fill a double array with zeros (used instead of memset nodes so the sequence is graph-safe).
+__global__ void zero_kernel(double* p, int64_t count) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0.0;
+}
+
+
+int resid_blocks(const int64_t n[3]) {
+  const int64_t rows = n[0] * n[1];
+  return int(rows < 4096 ? rows : 4096);
+}
+
+hipError_t launch_resid(const ResidArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(resid_kernel, dim3(resid_blocks(a.n)), dim3(RESID_NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partials, int nblocks, double inv_wsum, double* scalars, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, inv_wsum, scalars);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(zero_kernel, dim3(64), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
+}  // namespace mpois

@@ -1,0 +1,92 @@
+// Internal structures shared by the host plan layer and the device kernels.
+// Not part of the public C ABI (include/mpois.h).
+#pragma once
+#include <cstdint>
+
+namespace mpois {
+
+// Real line transforms.  Forward kinds map a real line of n values to n real
+// coefficients, inverse kinds map n coefficients back (all unnormalised).
+//   R2HC : real DFT, half-complex output (Re X_0..X_{n/2}, Im X_{(n-1)/2}..Im X_1)
+//   HC2R : inverse of R2HC times n
+//   DCT2 / DCT3 / DST2 / DST3 / DCT1 / DST1 : Table 1 of the paper
+enum Kind : int {
+  K_R2HC = 0, K_HC2R = 1, K_DCT2 = 2, K_DCT3 = 3,
+  K_DST2 = 4, K_DST3 = 5, K_DCT1 = 6, K_DST1 = 7
+};
+
+constexpr int MAX_STAGES = 16;
+
+// One Stockham stage: radix, product of the radices before it (ns), offset of
+// its twiddles e^{-2 pi i r k/(ns R)} (k < ns, 1 <= r < R) and, for odd radices
+// of 5 and above, of the R constants e^{2 pi i j/R} used by the codelet.
+struct Stage {
+  int radix;
+  int ns;
+  int tw_off;
+  int cs_off;
+};
+
+// Device description of the complex DFT that one axis's line transforms use.
+struct AxisDev {
+  int n;          // line length (real values)
+  int M;          // logical complex DFT length
+  int P;          // work length: M, or the power of two of the Bluestein convolution
+  int nstages;
+  int bluestein;  // 1: the length-M DFT is a chirp convolution of length P
+  int pad_;
+  const Stage* st;    // nstages entries, device memory
+  const void* tw;     // complex, working precision
+  const void* pre;    // e^{-i pi k/(2n)}, k < n (DCT2/DCT3/DST2/DST3 kinds)
+  const void* chirp;  // e^{-i pi m^2/M}, m < M (Bluestein)
+  const void* bhat;   // DFT_P of the conjugate chirp kernel, divided by P (Bluestein)
+  const void* cs;     // odd-radix constants
+};
+
+// One launch of the line-transform kernel along one axis.
+struct PassArgs {
+  const void* src;
+  void* dst;
+  int src_f64;          // element type of src: 1 double, 0 float
+  int dst_f64;          // element type of dst
+  int64_t nlines;       // number of lines along the axis
+  int64_t inner;        // element stride along a line (product of later dims)
+  int kind_f;           // transform applied first
+  int kind_b;           // transform applied after the eigenvalue scaling; -1 = none
+  int update;           // 1: dst <- dst + result - shift[0]  (dst is double)
+  int singular;         // 1: the all-zero mode gets coefficient 0
+  const double* shift;  // device scalar for update mode
+  const void* lam_this; // scaled eigenvalues along this axis (working precision)
+  const void* lam_a;    // scaled eigenvalues of the other axes, or null
+  const void* lam_b;
+  int64_t nb;           // length of the axis behind lam_b
+  AxisDev ax;
+};
+
+// Stencil residual over a (n0, n1, n2) box, all axes described by a closure.
+enum Closure : int { C_NONE = 0, C_PER = 1, C_DV = 2, C_DS = 3, C_NV = 4, C_NS = 5 };
+
+struct ResidArgs {
+  const double* phi;
+  const double* g;
+  void* r;              // output residual (or null), float or double
+  int r_f64;
+  int64_t n[3];
+  int clo[3];
+  double inv_h2[3];
+  const double* mg;     // device scalar subtracted from g (or null)
+  double* partials;     // 4 per block: sum w phi, sum w g, sum r^2, sum (g-mg)^2
+};
+
+// Reduced scalars kept on the device.
+enum Scalar : int {
+  S_WPHI = 0,   // sum w phi
+  S_WG = 1,     // sum w g
+  S_R2 = 2,     // sum r^2
+  S_G2 = 3,     // sum (g - m_g)^2
+  S_SHIFT = 4,  // sum w phi / sum w
+  S_MG = 5,     // sum w g / sum w
+  S_COUNT = 8
+};
+
+}  // namespace mpois

@@ -1,0 +1,575 @@
+// Line-transform kernel of the fast Poisson solver for gfx950 (CDNA4).
+//
+// line_pass: one HBM sweep along one axis.  A workgroup owns a tile of TL = 2*NP
+// adjacent lines: it loads them into LDS with coalesced accesses (rows when the
+// axis is contiguous, TL-wide column segments when it is strided), packs two
+// real lines into one complex sequence per pair, runs a Stockham DFT over all
+// pairs at once in LDS (or a Bluestein chirp convolution when the length has a
+// prime factor the codelets do not cover), unpacks, and stores.  The same
+// sweep can also apply the eigenvalue division and the inverse transform of
+// the axis, so the middle of a solve costs one sweep instead of two.
+//
+// The transforms are those of Table 2 of the paper (DFT for periodic axes,
+// DST-I/II for Dirichlet, DCT-I/II for Neumann, with DST-III/DCT-III as the
+// staggered-grid inverses); periodic axes use the real half-complex form of
+// the DFT so every sweep is real-to-real and in place.  The divisor is the sum
+// of the per-axis eigenvalues (Section 2.3), from Table 3 or Table 4.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mpois {
+
+template <typename T>
+struct cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+// multiply by -i
+template <typename T>
+__device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.im, -a.re}; }
+
+// Thread index hidden from loop-invariant code motion: per-item address
+// arithmetic is then recomputed where it is used instead of being hoisted out
+// of the phase / stage loops and kept live (which spills).
+__device__ __forceinline__ int opaque_tid() {
+  int t = int(threadIdx.x);
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// ----------------------------------------------------------------------------- codelets
+// Forward DFT (kernel e^{-2 pi i jk/R}) of R values held in registers.
+
+template <typename T>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T>* v) {
+  cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2], t2 = v[1] + v[3], t3 = mul_mi(v[1] - v[3]);
+  v[0] = t0 + t2;
+  v[2] = t0 - t2;
+  v[1] = t1 + t3;
+  v[3] = t1 - t3;
+}
+
+template <typename T>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  const T r2 = T(0.70710678118654752440084436210484903928483593768847);
+  cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4(e);
+  dft4(o);
+  // twiddles e^{-2 pi i k/8}, k = 0..3
+  cx<T> o1 = {(o[1].re + o[1].im) * r2, (o[1].im - o[1].re) * r2};
+  cx<T> o2 = mul_mi(o[2]);
+  cx<T> o3 = {(o[3].im - o[3].re) * r2, -(o[3].re + o[3].im) * r2};
+  v[0] = e[0] + o[0];
+  v[4] = e[0] - o[0];
+  v[1] = e[1] + o1;
+  v[5] = e[1] - o1;
+  v[2] = e[2] + o2;
+  v[6] = e[2] - o2;
+  v[3] = e[3] + o3;
+  v[7] = e[3] - o3;
+}
+
+template <typename T>
+__device__ __forceinline__ void dft3(cx<T>* v) {
+  const T s1 = T(0.86602540378443864676372317075293618347140262690519);
+  cx<T> t = v[1] + v[2], d = v[1] - v[2];
+  cx<T> m = {v[0].re - T(0.5) * t.re, v[0].im - T(0.5) * t.im};
+  v[0] = v[0] + t;
+  v[1] = {m.re + s1 * d.im, m.im - s1 * d.re};
+  v[2] = {m.re - s1 * d.im, m.im + s1 * d.re};
+}
+
+// Odd radix R >= 5 from the symmetric form: with s_j = v_j + v_{R-j} and
+// d_j = v_j - v_{R-j},  X_k = v_0 + sum_j s_j cos(2 pi jk/R) - i sum_j d_j sin(2 pi jk/R)
+// and X_{R-k} is the same with +i.  cs[j] = (cos, sin)(2 pi j/R).
+template <typename T, int R>
+__device__ __forceinline__ void dft_odd(cx<T>* v, const cx<T>* __restrict__ cs) {
+  constexpr int H = (R - 1) / 2;
+  cx<T> s[H], d[H];
+#pragma unroll
+  for (int j = 1; j <= H; ++j) {
+    s[j - 1] = v[j] + v[R - j];
+    d[j - 1] = v[j] - v[R - j];
+  }
+  cx<T> a0 = v[0];
+  cx<T> x0 = a0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) x0 = x0 + s[j];
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    cx<T> A = a0, B = {T(0), T(0)};
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const cx<T> w = cs[(j * k) % R];
+      A.re += s[j - 1].re * w.re;
+      A.im += s[j - 1].im * w.re;
+      B.re += d[j - 1].re * w.im;
+      B.im += d[j - 1].im * w.im;
+    }
+    v[k] = {A.re + B.im, A.im - B.re};
+    v[R - k] = {A.re - B.im, A.im + B.re};
+  }
+  v[0] = x0;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_any(cx<T>* v, const cx<T>* __restrict__ cs) {
+  if constexpr (R == 2) dft2(v);
+  else if constexpr (R == 3) dft3(v);
+  else if constexpr (R == 4) dft4(v);
+  else if constexpr (R == 8) dft8(v);
+  else dft_odd<T, R>(v, cs);
+}
+
+// ----------------------------------------------------------------------------- Stockham stage
+// Work buffer layout: Z[m * NP + p] holds element m of pair p.  All butterflies
+// of the stage are read into registers before the barrier and written after
+// it, so the stage runs in place in one buffer.
+template <typename T, int R, int NP, int NT, int PMAX>
+__device__ __forceinline__ void stage(cx<T>* Z, int P, int ns, const cx<T>* __restrict__ tw,
+                                      const cx<T>* __restrict__ cs) {
+  constexpr int NB = ((PMAX / R) * NP + NT - 1) / NT;
+  const int nbp = P / R;      // butterflies per pair
+  const int items = nbp * NP;
+  const int tid = opaque_tid();
+  cx<T> v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int item = tid + i * NT;
+    if (item < items) {
+      const int p = item % NP;
+      const int b = item / NP;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = Z[(b + r * nbp) * NP + p];
+      if (ns > 1) {
+        const int k = b % ns;
+        const cx<T>* w = tw + k * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r - 1]);
+      }
+      dft_any<T, R>(v[i], cs);
+    }
+  }
+  __syncthreads();
+  const int tid2 = opaque_tid();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int item = tid2 + i * NT;
+    if (item < items) {
+      const int p = item % NP;
+      const int b = item / NP;
+      const int k = b % ns;
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) Z[(base + r * ns) * NP + p] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Forward DFT of length P of every pair column of Z.
+template <typename T, int NP, int NT, int PMAX>
+__device__ __forceinline__ void dft_engine(cx<T>* Z, int P, int nstages, const Stage* __restrict__ stp,
+                                        const cx<T>* __restrict__ tw, const cx<T>* __restrict__ cs) {
+  for (int s = 0; s < nstages; ++s) {
+    const Stage st = stp[s];
+    const cx<T>* t = tw + st.tw_off;
+    const cx<T>* c = cs + st.cs_off;
+    switch (st.radix) {
+      case 2: stage<T, 2, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
+      case 3: stage<T, 3, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
+      case 4: stage<T, 4, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
+      case 5: stage<T, 5, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
+      case 7: stage<T, 7, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
+      case 8: stage<T, 8, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
+      case 11: stage<T, 11, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
+      case 13: stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
+      default: break;  // the planner only emits the radices above
+    }
+  }
+}
+
+// Element k of the length-M DFT of pair p after dft_full.
+template <typename T, int NP>
+__device__ __forceinline__ cx<T> dft_result(const cx<T>* Z, const AxisDev& ax, int k, int p) {
+  cx<T> z = Z[k * NP + p];
+  if (ax.bluestein) z = cmul(conj(z), static_cast<const cx<T>*>(ax.chirp)[k]);
+  return z;
+}
+
+// ----------------------------------------------------------------------------- tile access
+template <typename T>
+__device__ __forceinline__ T load_elem(const void* p, int64_t i, int f64) {
+  return f64 ? T(static_cast<const double*>(p)[i]) : T(static_cast<const float*>(p)[i]);
+}
+
+// Real tile X: element (t, j) of line t of the tile.
+struct TileGeom {
+  int contiguous;  // 1: rows (inner == 1); 0: columns
+  int pitch;       // row pitch for contiguous tiles
+};
+
+template <int TL>
+__device__ __forceinline__ int xi(const TileGeom& g, int t, int j) {
+  return g.contiguous ? t * g.pitch + j : j * TL + t;
+}
+
+// Halfcomplex entry k (complex X_k) of a real DFT stored as h[0..n-1].
+template <typename T, int TL>
+__device__ __forceinline__ cx<T> hc_get(const T* X, const TileGeom& g, int t, int k, int n) {
+  if (k == 0) return {X[xi<TL>(g, t, 0)], T(0)};
+  if (2 * k < n) return {X[xi<TL>(g, t, k)], X[xi<TL>(g, t, n - k)]};
+  if (2 * k == n) return {X[xi<TL>(g, t, k)], T(0)};
+  return {X[xi<TL>(g, t, n - k)], -X[xi<TL>(g, t, k)]};
+}
+
+// DCT-II reorder: v_m = x_{perm(m)} (even indices ascending, then odd descending).
+__device__ __forceinline__ int perm_even_odd(int m, int n) {
+  return (2 * m <= n - 1) ? 2 * m : 2 * (n - 1 - m) + 1;
+}
+
+// Packing: the complex input of the length-M DFT for pair p at index m
+// (times the chirp for Bluestein, conjugated for inverse kinds).
+template <typename T, int TL, int kind>
+__device__ __forceinline__ cx<T> pack_value(const T* X, const TileGeom& g, const AxisDev& ax, int m, int p) {
+  const int n = ax.n, M = ax.M;
+  const int t0 = 2 * p, t1 = 2 * p + 1;
+  cx<T> val = {T(0), T(0)};
+  if (m >= M) return val;
+  switch (kind) {
+    case K_R2HC:
+      val = {X[xi<TL>(g, t0, m)], X[xi<TL>(g, t1, m)]};
+      break;
+    case K_DCT2:
+    case K_DST2: {
+      const int j = perm_even_odd(m, n);
+      val = {X[xi<TL>(g, t0, j)], X[xi<TL>(g, t1, j)]};
+      if (kind == K_DST2 && (j & 1)) val = {-val.re, -val.im};
+      break;
+    }
+    case K_DCT1: {
+      const int j = (m < n) ? m : M - m;
+      val = {X[xi<TL>(g, t0, j)], X[xi<TL>(g, t1, j)]};
+      break;
+    }
+    case K_DST1: {
+      if (m == 0 || m == n + 1) break;
+      if (m <= n) {
+        val = {X[xi<TL>(g, t0, m - 1)], X[xi<TL>(g, t1, m - 1)]};
+      } else {
+        const int j = M - m - 1;
+        val = {-X[xi<TL>(g, t0, j)], -X[xi<TL>(g, t1, j)]};
+      }
+      break;
+    }
+    case K_HC2R: {
+      const cx<T> a = hc_get<T, TL>(X, g, t0, m, n);
+      const cx<T> b = hc_get<T, TL>(X, g, t1, m, n);
+      val = {a.re - b.im, -(a.im + b.re)};  // conj(a + i b)
+      break;
+    }
+    case K_DCT3:
+    case K_DST3: {
+      // V_k = e^{+i pi k/(2n)} (c_k - i c_{n-k}), c_n = 0; DST3 reverses c first.
+      const int k = m;
+      const int ka = (kind == K_DST3) ? n - 1 - k : k;
+      const T c0k = X[xi<TL>(g, t0, ka)], c1k = X[xi<TL>(g, t1, ka)];
+      T c0n = T(0), c1n = T(0);
+      if (k > 0) {
+        const int kb = (kind == K_DST3) ? k - 1 : n - k;
+        c0n = X[xi<TL>(g, t0, kb)];
+        c1n = X[xi<TL>(g, t1, kb)];
+      }
+      const cx<T> e = conj(static_cast<const cx<T>*>(ax.pre)[k]);
+      const cx<T> v0 = cmul(e, cx<T>{c0k, -c0n});
+      const cx<T> v1 = cmul(e, cx<T>{c1k, -c1n});
+      val = {v0.re - v1.im, -(v0.im + v1.re)};  // conj(v0 + i v1)
+      break;
+    }
+    default:
+      break;
+  }
+  if (ax.bluestein) val = cmul(val, static_cast<const cx<T>*>(ax.chirp)[m]);
+  return val;
+}
+
+// Unpacking: output coefficient k of line t from the DFT result.
+template <typename T, int NP, int kind>
+__device__ __forceinline__ T unpack_value(const cx<T>* Z, const AxisDev& ax, int t, int k) {
+  const int n = ax.n, M = ax.M;
+  const int p = t >> 1, w = t & 1;
+  switch (kind) {
+    case K_R2HC:
+    case K_DCT2:
+    case K_DST2: {
+      int kk = k;
+      if (kind == K_R2HC && 2 * k > n) kk = n - k;
+      if (kind == K_DST2) kk = n - 1 - k;
+      const cx<T> zk = dft_result<T, NP>(Z, ax, kk, p);
+      const cx<T> zr = conj(dft_result<T, NP>(Z, ax, kk == 0 ? 0 : M - kk, p));
+      // line 0: (zk + zr)/2 ; line 1: (zk - zr)/(2i)
+      cx<T> V;
+      if (w == 0) V = {T(0.5) * (zk.re + zr.re), T(0.5) * (zk.im + zr.im)};
+      else V = {T(0.5) * (zk.im - zr.im), -T(0.5) * (zk.re - zr.re)};
+      if (kind == K_R2HC) return (2 * k <= n) ? V.re : V.im;
+      const cx<T> e = static_cast<const cx<T>*>(ax.pre)[kk];
+      return T(2) * (e.re * V.re - e.im * V.im);
+    }
+    case K_DCT1: {
+      const cx<T> z = dft_result<T, NP>(Z, ax, k, p);
+      return w ? z.im : z.re;
+    }
+    case K_DST1: {
+      const cx<T> z = dft_result<T, NP>(Z, ax, k + 1, p);
+      return w ? z.re : -z.im;
+    }
+    case K_HC2R: {
+      const cx<T> z = dft_result<T, NP>(Z, ax, k, p);
+      return w ? -z.im : z.re;
+    }
+    case K_DCT3:
+    case K_DST3: {
+      const int q = (k & 1) ? n - 1 - (k >> 1) : (k >> 1);
+      const cx<T> z = dft_result<T, NP>(Z, ax, q, p);
+      T v = w ? -z.im : z.re;
+      if (kind == K_DST3 && (k & 1)) v = -v;
+      return v;
+    }
+    default:
+      return T(0);
+  }
+}
+
+// X (real tile) -> Z (packed complex), through registers.
+template <typename T, int NP, int NT, int PMAX, int kind>
+__device__ __forceinline__ void pack_k(T* X, cx<T>* Z, const TileGeom& g, const AxisDev& ax) {
+  constexpr int TL = 2 * NP;
+  constexpr int E = (PMAX * NP + NT - 1) / NT;
+  const int items = ax.P * NP;
+  const int tid = opaque_tid();
+  cx<T> v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int item = tid + i * NT;
+    if (item < items) v[i] = pack_value<T, TL, kind>(X, g, ax, item / NP, item % NP);
+  }
+  __syncthreads();
+  const int tid2 = opaque_tid();
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int item = tid2 + i * NT;
+    if (item < items) Z[item] = v[i];
+  }
+  __syncthreads();
+}
+
+template <typename T, int NP, int NT, int PMAX>
+__device__ __forceinline__ void pack(T* X, cx<T>* Z, const TileGeom& g, int kind, const AxisDev& ax) {
+  switch (kind) {
+    case K_R2HC: pack_k<T, NP, NT, PMAX, K_R2HC>(X, Z, g, ax); break;
+    case K_HC2R: pack_k<T, NP, NT, PMAX, K_HC2R>(X, Z, g, ax); break;
+    case K_DCT2: pack_k<T, NP, NT, PMAX, K_DCT2>(X, Z, g, ax); break;
+    case K_DCT3: pack_k<T, NP, NT, PMAX, K_DCT3>(X, Z, g, ax); break;
+    case K_DST2: pack_k<T, NP, NT, PMAX, K_DST2>(X, Z, g, ax); break;
+    case K_DST3: pack_k<T, NP, NT, PMAX, K_DST3>(X, Z, g, ax); break;
+    case K_DCT1: pack_k<T, NP, NT, PMAX, K_DCT1>(X, Z, g, ax); break;
+    default: pack_k<T, NP, NT, PMAX, K_DST1>(X, Z, g, ax); break;
+  }
+}
+
+// Z -> X, through registers, optionally dividing by the eigenvalue sum.
+template <typename T, int NP, int NT, int PMAX, int kind>
+__device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const TileGeom& g, const AxisDev& ax, const PassArgs& a,
+                                         int64_t l0, bool scale) {
+  constexpr int TL = 2 * NP;
+  constexpr int E = (2 * PMAX * NP + NT - 1) / NT;
+  static_assert(NT % TL == 0, "thread count must be a multiple of the tile width");
+  const int n = ax.n;
+  const int items = n * TL;
+  const int tid = opaque_tid();
+  const int t = tid % TL;  // fixed per thread
+  T lam_other = T(0);
+  bool zero_line = false;
+  if (scale) {
+    const int64_t l = l0 + t;
+    const T* la = static_cast<const T*>(a.lam_a);
+    const T* lb = static_cast<const T*>(a.lam_b);
+    if (l < a.nlines) {
+      if (lb) lam_other = la[l / a.nb] + lb[l % a.nb];
+      else if (la) lam_other = la[l];
+    }
+    zero_line = a.singular && (l == 0);
+  }
+  const T* lt = static_cast<const T*>(a.lam_this);
+  T v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int item = tid + i * NT;
+    if (item < items) {
+      const int k = item / TL;
+      T x = unpack_value<T, NP, kind>(Z, ax, t, k);
+      if (scale) {
+        const T lam = lam_other + lt[k];
+        x = (zero_line && k == 0) ? T(0) : x / lam;
+      }
+      v[i] = x;
+    }
+  }
+  __syncthreads();
+  const int tid2 = opaque_tid();
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int item = tid2 + i * NT;
+    if (item < items) X[xi<TL>(g, tid2 % TL, item / TL)] = v[i];
+  }
+  __syncthreads();
+}
+
+template <typename T, int NP, int NT, int PMAX>
+__device__ __forceinline__ void unpack(cx<T>* Z, T* X, const TileGeom& g, int kind, const AxisDev& ax,
+                                       const PassArgs& a, int64_t l0, bool scale) {
+  switch (kind) {
+    case K_R2HC: unpack_k<T, NP, NT, PMAX, K_R2HC>(Z, X, g, ax, a, l0, scale); break;
+    case K_HC2R: unpack_k<T, NP, NT, PMAX, K_HC2R>(Z, X, g, ax, a, l0, scale); break;
+    case K_DCT2: unpack_k<T, NP, NT, PMAX, K_DCT2>(Z, X, g, ax, a, l0, scale); break;
+    case K_DCT3: unpack_k<T, NP, NT, PMAX, K_DCT3>(Z, X, g, ax, a, l0, scale); break;
+    case K_DST2: unpack_k<T, NP, NT, PMAX, K_DST2>(Z, X, g, ax, a, l0, scale); break;
+    case K_DST3: unpack_k<T, NP, NT, PMAX, K_DST3>(Z, X, g, ax, a, l0, scale); break;
+    case K_DCT1: unpack_k<T, NP, NT, PMAX, K_DCT1>(Z, X, g, ax, a, l0, scale); break;
+    default: unpack_k<T, NP, NT, PMAX, K_DST1>(Z, X, g, ax, a, l0, scale); break;
+  }
+}
+
+template <typename T, int NP, int NT, int PMAX>
+__global__ void __launch_bounds__(NT) line_pass(PassArgs a) {
+  constexpr int TL = 2 * NP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* X = reinterpret_cast<T*>(smem);
+  cx<T>* Z = reinterpret_cast<cx<T>*>(smem);
+  const AxisDev& ax = a.ax;
+  const int n = ax.n;
+  const int64_t B = a.inner;
+  const int64_t l0 = int64_t(blockIdx.x) * TL;
+  TileGeom g;
+  g.contiguous = (B == 1);
+  g.pitch = n | 1;
+
+  // ---- load
+  if (g.contiguous) {
+    const int64_t lend = (l0 + TL < a.nlines) ? l0 + TL : a.nlines;
+    const int valid = int((lend - l0) * n);
+    const int64_t base = l0 * n;
+    for (int f = threadIdx.x; f < TL * n; f += NT) {
+      const int t = f / n, j = f - t * n;
+      X[t * g.pitch + j] = (f < valid) ? load_elem<T>(a.src, base + f, a.src_f64) : T(0);
+    }
+  } else {
+    const int t = threadIdx.x % TL;
+    const int64_t l = l0 + t;
+    const bool ok = l < a.nlines;
+    const int64_t base = ok ? (l / B) * (int64_t(n) * B) + (l % B) : 0;
+    for (int j = threadIdx.x / TL; j < n; j += NT / TL)
+      X[j * TL + t] = ok ? load_elem<T>(a.src, base + int64_t(j) * B, a.src_f64) : T(0);
+  }
+  __syncthreads();
+
+  // ---- forward transform, and optionally eigenvalue division + inverse transform.
+  // The phases and the two DFTs of a Bluestein convolution share one copy of
+  // the DFT engine code (runtime loops, not unrolled).
+  const cx<T>* tw = static_cast<const cx<T>*>(ax.tw);
+  const cx<T>* cs = static_cast<const cx<T>*>(ax.cs);
+  const cx<T>* bh = static_cast<const cx<T>*>(ax.bhat);
+  const int nphase = a.kind_b >= 0 ? 2 : 1;
+  const int nrep = ax.bluestein ? 2 : 1;
+  for (int phase = 0; phase < nphase; ++phase) {
+    const int kind = phase == 0 ? a.kind_f : a.kind_b;
+    pack<T, NP, NT, PMAX>(X, Z, g, kind, ax);
+    // Stockham DFT; for Bluestein: DFT, times the kernel spectrum, conjugate, DFT
+    // (the unpacker conjugates and applies the chirp).
+    for (int rep = 0; rep < nrep; ++rep) {
+      if (rep == 1) {
+        const int items = ax.P * NP;
+        for (int item = threadIdx.x; item < items; item += NT) Z[item] = conj(cmul(Z[item], bh[item / NP]));
+        __syncthreads();
+      }
+      dft_engine<T, NP, NT, PMAX>(Z, ax.P, ax.nstages, ax.st, tw, cs);
+    }
+    unpack<T, NP, NT, PMAX>(Z, X, g, kind, ax, a, l0, phase == 0 && nphase == 2);
+  }
+
+  // ---- store
+  if (g.contiguous) {
+    const int64_t lend = (l0 + TL < a.nlines) ? l0 + TL : a.nlines;
+    const int valid = int((lend - l0) * n);
+    const int64_t base = l0 * n;
+    for (int f = threadIdx.x; f < valid; f += NT) {
+      const int t = f / n, j = f - t * n;
+      const T x = X[t * g.pitch + j];
+      if (a.update) {
+        double* d = static_cast<double*>(a.dst);
+        d[base + f] = d[base + f] + double(x) - a.shift[0];
+      } else if (a.dst_f64) {
+        static_cast<double*>(a.dst)[base + f] = double(x);
+      } else {
+        static_cast<float*>(a.dst)[base + f] = float(x);
+      }
+    }
+  } else {
+    const int t = threadIdx.x % TL;
+    const int64_t l = l0 + t;
+    if (l < a.nlines) {
+      const int64_t base = (l / B) * (int64_t(n) * B) + (l % B);
+      for (int j = threadIdx.x / TL; j < n; j += NT / TL) {
+        const T x = X[j * TL + t];
+        const int64_t o = base + int64_t(j) * B;
+        if (a.update) {
+          double* d = static_cast<double*>(a.dst);
+          d[o] = d[o] + double(x) - a.shift[0];
+        } else if (a.dst_f64) {
+          static_cast<double*>(a.dst)[o] = double(x);
+        } else {
+          static_cast<float*>(a.dst)[o] = float(x);
+        }
+      }
+    }
+  }
+}
+
+
+template <typename T, int NP, int NT, int PMAX>
+hipError_t launch_lp(const PassArgs& a, hipStream_t s, size_t lds) {
+  constexpr int64_t TL = 2 * NP;
+  const int64_t blocks = (a.nlines + TL - 1) / TL;
+  hipLaunchKernelGGL((line_pass<T, NP, NT, PMAX>), dim3(unsigned(blocks)), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int NP, int NT, int PMAX>
+hipError_t prepare_lp() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass<T, NP, NT, PMAX>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+}  // namespace mpois

@@ -1,0 +1,875 @@
+// Host side of the solver: argument validation, per-axis transform planning,
+// FP64 eigenvalue and twiddle tables, workspace, the launch sequence of one
+// solve (Sections 2.1-2.3 of the paper) and the FP64 refinement loop.
+#include "mpois.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "tune.h"
+
+namespace mpois {
+int num_kernel_cfgs();
+void kernel_cfg(int i, int* f64, int* np, int* nt, int* pmax);
+size_t line_pass_lds(int cfg, int n, int P);
+hipError_t prepare_kernels();
+hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s);
+int resid_blocks(const int64_t n[3]);
+hipError_t launch_resid(const ResidArgs& a, hipStream_t s);
+hipError_t launch_finalize(const double* partials, int nblocks, double inv_wsum, double* scalars, hipStream_t s);
+hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
+}  // namespace mpois
+
+using namespace mpois;
+
+namespace {
+
+constexpr int kMaxLds = 160 * 1024;
+constexpr int kMaxResidBlocks = 4096;
+const int kRadices[] = {8, 4, 2, 3, 5, 7, 11, 13};
+
+// ---------------------------------------------------------------------------- exact angles
+// sin / cos of pi * num / den with num reduced modulo 2 den before scaling.
+double sinpi_frac(int64_t num, int64_t den) {
+  int64_t m = num % (2 * den);
+  if (m < 0) m += 2 * den;
+  return std::sin(M_PI * double(m) / double(den));
+}
+double cospi_frac(int64_t num, int64_t den) {
+  int64_t m = num % (2 * den);
+  if (m < 0) m += 2 * den;
+  return std::cos(M_PI * double(m) / double(den));
+}
+
+// ---------------------------------------------------------------------------- per-axis math
+// Table 2: forward / backward line transform of an axis.
+void axis_kinds(int bc, int grid, int* kf, int* kb) {
+  if (bc == MPOIS_PERIODIC) { *kf = K_R2HC; *kb = K_HC2R; return; }
+  if (bc == MPOIS_DIRICHLET) {
+    if (grid == MPOIS_VERTEX) { *kf = K_DST1; *kb = K_DST1; }
+    else { *kf = K_DST2; *kb = K_DST3; }
+    return;
+  }
+  if (grid == MPOIS_VERTEX) { *kf = K_DCT1; *kb = K_DCT1; }
+  else { *kf = K_DCT2; *kb = K_DCT3; }
+}
+
+// Complex DFT length used by a line transform of n points.
+int64_t axis_dft_length(int kind, int64_t n) {
+  if (kind == K_DCT1) return 2 * (n - 1);
+  if (kind == K_DST1) return 2 * (n + 1);
+  return n;
+}
+
+// Table 2: the factor in front of the backward transform.
+double axis_norm(int bc, int grid, int64_t n) {
+  if (bc == MPOIS_PERIODIC) return 1.0 / double(n);
+  if (bc == MPOIS_DIRICHLET) return grid == MPOIS_VERTEX ? 1.0 / (2.0 * double(n + 1)) : 1.0 / (2.0 * double(n));
+  return grid == MPOIS_VERTEX ? 1.0 / (2.0 * double(n - 1)) : 1.0 / (2.0 * double(n));
+}
+
+// Domain length implied by spacing h on the grids of Section 2.1.
+double axis_length(int bc, int grid, int64_t n, double h) {
+  if (bc == MPOIS_PERIODIC || grid == MPOIS_STAGGERED) return double(n) * h;
+  if (bc == MPOIS_DIRICHLET) return double(n + 1) * h;
+  return double(n - 1) * h;
+}
+
+// Table 3 (pseudo-spectral) / Table 4 (finite differences), k = 0..n-1.  The
+// periodic pseudo-spectral branch uses the aliased wavenumber min(k, n-k).
+void axis_eigs(int bc, int grid, int approx, int64_t n, double h, double* out) {
+  if (approx == MPOIS_SPECTRAL) {
+    const double L = axis_length(bc, grid, n, h);
+    for (int64_t k = 0; k < n; ++k) {
+      double w;
+      if (bc == MPOIS_PERIODIC) w = 2.0 * M_PI * double(std::min(k, n - k)) / L;
+      else if (bc == MPOIS_DIRICHLET) w = M_PI * double(k + 1) / L;
+      else w = M_PI * double(k) / L;
+      out[k] = -w * w;
+    }
+    return;
+  }
+  for (int64_t k = 0; k < n; ++k) {
+    double s;
+    if (bc == MPOIS_PERIODIC) s = sinpi_frac(k, n);
+    else if (bc == MPOIS_DIRICHLET) s = grid == MPOIS_VERTEX ? sinpi_frac(k + 1, 2 * (n + 1)) : sinpi_frac(k + 1, 2 * n);
+    else s = grid == MPOIS_VERTEX ? sinpi_frac(k, 2 * (n - 1)) : sinpi_frac(k, 2 * n);
+    const double v = 2.0 * s / h;
+    out[k] = -v * v;
+  }
+}
+
+// Factor M over the codelet radices; returns false if a larger prime remains.
+bool factor_radices(int64_t M, std::vector<int>* out) {
+  out->clear();
+  int64_t m = M;
+  for (int r : kRadices) {
+    while (m % r == 0) {
+      out->push_back(r);
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+
+int64_t next_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Iterative radix-2 FFT (sign -1) in FP64 for the Bluestein kernel spectrum.
+void host_fft(std::vector<std::complex<double>>& a) {
+  const size_t n = a.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    for (size_t i = 0; i < n; i += len) {
+      for (size_t k = 0; k < len / 2; ++k) {
+        const double ang = -2.0 * M_PI * double(k) / double(len);
+        const std::complex<double> w(std::cos(ang), std::sin(ang));
+        const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+struct AxisShape {
+  int kind_f = 0, kind_b = 0;
+  int64_t M = 0, P = 0;
+  bool bluestein = false;
+  std::vector<int> radices;
+};
+
+AxisShape plan_axis_shape(int bc, int grid, int64_t n) {
+  AxisShape s;
+  axis_kinds(bc, grid, &s.kind_f, &s.kind_b);
+  s.M = axis_dft_length(s.kind_f, n);
+  if (factor_radices(s.M, &s.radices)) {
+    s.P = s.M;
+  } else {
+    s.bluestein = true;
+    s.P = next_pow2(2 * s.M - 1);
+    factor_radices(s.P, &s.radices);
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------- device tables
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct AxisTables {
+  AxisShape shape;
+  int64_t n = 0;
+  DevBuf tw, pre, chirp, bhat, cs, stages;
+  AxisDev dev{};
+};
+
+template <typename T>
+void to_prec(const std::vector<std::complex<double>>& src, std::vector<T>* dst) {
+  dst->resize(src.size() * 2);
+  for (size_t i = 0; i < src.size(); ++i) {
+    (*dst)[2 * i] = T(src[i].real());
+    (*dst)[2 * i + 1] = T(src[i].imag());
+  }
+}
+
+// ---------------------------------------------------------------------------- plan
+struct Pass {
+  PassArgs args{};
+  int cfg = 0;
+  int axis = 0;   // axis this pass transforms
+};
+
+struct SubPlan {
+  int ndim = 0;
+  int64_t n[3] = {1, 1, 1};     // padded to 3D: leading unit dims
+  int64_t npts = 0;
+  int bc[3] = {0, 0, 0}, grid[3] = {0, 0, 0};
+  double h[3] = {1, 1, 1};
+  bool singular = false;
+  double wsum = 0;              // sum of gauge weights
+  std::vector<int> axis_table;  // index into Plan::tables per (real) axis
+  std::vector<DevBuf> lam;      // scaled eigenvalues per axis (working precision)
+  std::vector<Pass> passes;     // forward ... fused ... inverse
+  ResidArgs resid{};
+};
+
+// Per-launch record of a profiled execute.
+struct ProfRec {
+  int kernel;      // line-pass configuration index, or 100 residual, 101 finalisation
+  double bytes;    // algorithmic HBM bytes of the launch
+  hipEvent_t end;  // recorded after the launch
+};
+
+struct Graph {
+  const void* rhs = nullptr;
+  void* phi = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct mpois_plan_s {
+  int approx = 0, prec = 0, max_iter = 1;
+  double rtol = 0;
+  unsigned flags = 0;
+  int device = 0;
+  bool f64work = true;
+  std::vector<AxisTables> tables;
+  std::map<std::pair<int, int64_t>, int> table_index;  // (kind_f, n) -> tables index... keyed with bc/grid
+  std::vector<SubPlan> subs;
+  DevBuf work;       // FP32 working array (refinement)
+  DevBuf partials;   // resid partials
+  DevBuf scalars;    // S_COUNT doubles per grid
+  size_t bytes = 0;
+  const void* last_rhs = nullptr;
+  void* last_phi = nullptr;
+  std::vector<const void*> last_rhs_b;
+  std::vector<void*> last_phi_b;
+  int last_iters = 0;
+  Graph graph;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t prof_start = nullptr;
+  std::vector<ProfRec> prof;
+  size_t prof_used = 0;
+  bool profiling = false;
+};
+
+namespace {
+
+bool fault_alloc() {
+  const char* e = std::getenv("MPOIS_FAULT_ALLOC");
+  return e && e[0] == '1';
+}
+
+mpois_status dev_alloc(mpois_plan_s* pl, DevBuf* b, size_t bytes) {
+  if (bytes == 0) return MPOIS_OK;
+  if (fault_alloc()) return MPOIS_ERR_NOMEM;
+  if (hipMalloc(&b->p, bytes) != hipSuccess) {
+    b->p = nullptr;
+    (void)hipGetLastError();
+    return MPOIS_ERR_NOMEM;
+  }
+  b->bytes = bytes;
+  pl->bytes += bytes;
+  return MPOIS_OK;
+}
+
+template <typename V>
+mpois_status dev_upload(mpois_plan_s* pl, DevBuf* b, const std::vector<V>& host) {
+  if (host.empty()) return MPOIS_OK;
+  mpois_status st = dev_alloc(pl, b, host.size() * sizeof(V));
+  if (st != MPOIS_OK) return st;
+  if (hipMemcpy(b->p, host.data(), b->bytes, hipMemcpyHostToDevice) != hipSuccess) return MPOIS_ERR_DEVICE;
+  return MPOIS_OK;
+}
+
+void dev_free(DevBuf* b) {
+  if (b->p) (void)hipFree(b->p);
+  b->p = nullptr;
+  b->bytes = 0;
+}
+
+template <typename T>
+mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
+  const AxisShape& s = at->shape;
+  const int64_t n = at->n;
+  // Stockham stages and their twiddles e^{-2 pi i r k/(ns R)}.
+  std::vector<std::complex<double>> tw, cs;
+  AxisDev& d = at->dev;
+  d.n = int(n);
+  d.M = int(s.M);
+  d.P = int(s.P);
+  d.bluestein = s.bluestein ? 1 : 0;
+  d.nstages = int(s.radices.size());
+  std::vector<Stage> stages(s.radices.size() + 1);
+  int64_t ns = 1;
+  for (size_t i = 0; i < s.radices.size(); ++i) {
+    const int R = s.radices[i];
+    Stage& st = stages[i];
+    st.radix = R;
+    st.ns = int(ns);
+    st.tw_off = int(tw.size());
+    for (int64_t k = 0; k < ns; ++k)
+      for (int r = 1; r < R; ++r) {
+        const int64_t num = 2 * int64_t(r) * k, den = ns * R;
+        tw.emplace_back(cospi_frac(num, den), -sinpi_frac(num, den));
+      }
+    st.cs_off = int(cs.size());
+    if (R >= 5 && (R & 1)) {
+      for (int j = 0; j < R; ++j) cs.emplace_back(cospi_frac(2 * j, R), sinpi_frac(2 * j, R));
+    }
+    ns *= R;
+  }
+  if (tw.empty()) tw.emplace_back(1.0, 0.0);
+  if (cs.empty()) cs.emplace_back(1.0, 0.0);
+  mpois_status st = dev_upload(pl, &at->stages, stages);
+  if (st != MPOIS_OK) return st;
+  std::vector<T> h;
+  to_prec(tw, &h);
+  if ((st = dev_upload(pl, &at->tw, h)) != MPOIS_OK) return st;
+  to_prec(cs, &h);
+  if ((st = dev_upload(pl, &at->cs, h)) != MPOIS_OK) return st;
+  // e^{-i pi k/(2n)} for the DCT-II family.
+  if (s.kind_f == K_DCT2 || s.kind_f == K_DST2) {
+    std::vector<std::complex<double>> pre(static_cast<size_t>(n));
+    for (int64_t k = 0; k < n; ++k) pre[k] = {cospi_frac(k, 2 * n), -sinpi_frac(k, 2 * n)};
+    to_prec(pre, &h);
+    if ((st = dev_upload(pl, &at->pre, h)) != MPOIS_OK) return st;
+  }
+  // Bluestein: chirp w_m = e^{-i pi m^2/M}, kernel b = conj(w) wrapped, its DFT / P.
+  if (s.bluestein) {
+    std::vector<std::complex<double>> w(size_t(s.M)), b(size_t(s.P), {0.0, 0.0});
+    for (int64_t m = 0; m < s.M; ++m) {
+      const int64_t q = (m * m) % (2 * s.M);
+      w[m] = {cospi_frac(q, s.M), -sinpi_frac(q, s.M)};
+    }
+    for (int64_t m = 0; m < s.M; ++m) b[m] = std::conj(w[m]);
+    for (int64_t m = 1; m < s.M; ++m) b[s.P - m] = std::conj(w[m]);
+    host_fft(b);
+    for (auto& x : b) x /= double(s.P);
+    to_prec(w, &h);
+    if ((st = dev_upload(pl, &at->chirp, h)) != MPOIS_OK) return st;
+    to_prec(b, &h);
+    if ((st = dev_upload(pl, &at->bhat, h)) != MPOIS_OK) return st;
+  }
+  d.st = static_cast<const Stage*>(at->stages.p);
+  d.tw = at->tw.p;
+  d.cs = at->cs.p;
+  d.pre = at->pre.p;
+  d.chirp = at->chirp.p;
+  d.bhat = at->bhat.p;
+  return MPOIS_OK;
+}
+
+// Largest-tile kernel configuration of the working precision that holds the line.
+int default_cfg(bool f64, int n, int P) {
+  int best = -1, best_np = 0;
+  for (int i = 0; i < num_kernel_cfgs(); ++i) {
+    int cf64, np, nt, pmax;
+    kernel_cfg(i, &cf64, &np, &nt, &pmax);
+    if ((cf64 != 0) != f64 || P > pmax) continue;
+    if (line_pass_lds(i, n, P) > size_t(kMaxLds)) continue;
+    if (np > best_np) {
+      best = i;
+      best_np = np;
+    }
+  }
+  return best;
+}
+
+int closure_of(int bc, int grid) {
+  if (bc == MPOIS_PERIODIC) return C_PER;
+  if (bc == MPOIS_DIRICHLET) return grid == MPOIS_VERTEX ? C_DV : C_DS;
+  return grid == MPOIS_VERTEX ? C_NV : C_NS;
+}
+
+mpois_status validate_one(const mpois_grid_desc* g, int approx, int prec, int max_iter) {
+  if (!g) return MPOIS_ERR_INVALID;
+  if (g->ndim < 1 || g->ndim > 3) return MPOIS_ERR_INVALID;
+  if (approx != MPOIS_SPECTRAL && approx != MPOIS_FD2) return MPOIS_ERR_INVALID;
+  if (prec != MPOIS_F64 && prec != MPOIS_F32 && prec != MPOIS_F32_REFINE) return MPOIS_ERR_INVALID;
+  int64_t total = 1;
+  for (int d = 0; d < g->ndim; ++d) {
+    const int b0 = g->bc[d][0], b1 = g->bc[d][1];
+    if (b0 < 0 || b0 > 2 || b1 < 0 || b1 > 2) return MPOIS_ERR_INVALID;
+    if ((b0 == MPOIS_PERIODIC) != (b1 == MPOIS_PERIODIC)) return MPOIS_ERR_INVALID;
+    if (g->grid[d] != MPOIS_VERTEX && g->grid[d] != MPOIS_STAGGERED) return MPOIS_ERR_INVALID;
+    if (!(std::isfinite(g->h[d]) && g->h[d] > 0)) return MPOIS_ERR_INVALID;
+    if (g->n[d] < 1) return MPOIS_ERR_INVALID;
+    if (b0 == MPOIS_NEUMANN && g->grid[d] == MPOIS_VERTEX && g->n[d] < 2) return MPOIS_ERR_INVALID;
+    if (b0 != b1) return MPOIS_ERR_UNSUPPORTED;  // mixed Dirichlet/Neumann on one axis
+    if (g->n[d] > (1 << 20)) return MPOIS_ERR_UNSUPPORTED;
+    total *= g->n[d];
+    if (total > (int64_t(1) << 34)) return MPOIS_ERR_UNSUPPORTED;
+  }
+  if (prec == MPOIS_F32_REFINE) {
+    if (approx == MPOIS_SPECTRAL) return MPOIS_ERR_UNSUPPORTED;
+    if (max_iter < 1 || max_iter > 64) return MPOIS_ERR_INVALID;
+  }
+  // every axis must fit one of the kernel shapes
+  for (int d = 0; d < g->ndim; ++d) {
+    AxisShape s = plan_axis_shape(g->bc[d][0], g->grid[d], g->n[d]);
+    if (default_cfg(prec == MPOIS_F64, int(g->n[d]), int(s.P)) < 0) return MPOIS_ERR_UNSUPPORTED;
+  }
+  return MPOIS_OK;
+}
+
+mpois_status device_ready(int* dev) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    return MPOIS_ERR_DEVICE;
+  }
+  if (hipGetDevice(dev) != hipSuccess) return MPOIS_ERR_DEVICE;
+  static bool prepared = false;
+  if (!prepared) {
+    if (prepare_kernels() != hipSuccess) return MPOIS_ERR_DEVICE;
+    prepared = true;
+  }
+  return MPOIS_OK;
+}
+
+template <typename T>
+mpois_status upload_lam(mpois_plan_s* pl, DevBuf* b, const std::vector<double>& lam) {
+  std::vector<T> h(lam.size());
+  for (size_t i = 0; i < lam.size(); ++i) h[i] = T(lam[i]);
+  return dev_upload(pl, b, h);
+}
+
+int table_for(mpois_plan_s* pl, int bc, int grid, int64_t n, mpois_status* st) {
+  const int key_kind = bc * 2 + (bc == MPOIS_PERIODIC ? 0 : grid);
+  auto key = std::make_pair(key_kind, n);
+  auto it = pl->table_index.find(key);
+  if (it != pl->table_index.end()) return it->second;
+  AxisTables at;
+  at.shape = plan_axis_shape(bc, grid, n);
+  at.n = n;
+  pl->tables.push_back(at);
+  const int idx = int(pl->tables.size()) - 1;
+  *st = pl->f64work ? build_axis_tables<double>(pl, &pl->tables[idx]) : build_axis_tables<float>(pl, &pl->tables[idx]);
+  pl->table_index[key] = idx;
+  return idx;
+}
+
+mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) {
+  const int D = g->ndim;
+  sp->ndim = D;
+  // pad to 3D with leading unit axes
+  for (int d = 0; d < D; ++d) {
+    const int e = 3 - D + d;
+    sp->n[e] = g->n[d];
+    sp->h[e] = g->h[d];
+    sp->bc[e] = g->bc[d][0];
+    sp->grid[e] = g->bc[d][0] == MPOIS_PERIODIC ? MPOIS_VERTEX : g->grid[d];
+  }
+  sp->npts = sp->n[0] * sp->n[1] * sp->n[2];
+  sp->singular = true;
+  for (int d = 0; d < D; ++d)
+    if (g->bc[d][0] == MPOIS_DIRICHLET) sp->singular = false;
+  // weights sum
+  double wsum = 1.0;
+  for (int d = 0; d < D; ++d) {
+    const int64_t n = g->n[d];
+    wsum *= (g->bc[d][0] == MPOIS_NEUMANN && g->grid[d] == MPOIS_VERTEX) ? double(n - 1) : double(n);
+  }
+  sp->wsum = wsum;
+  // tables, eigenvalues scaled by the product of the backward normalisations
+  double c = 1.0;
+  for (int d = 0; d < D; ++d) c *= axis_norm(g->bc[d][0], g->grid[d], g->n[d]);
+  mpois_status st = MPOIS_OK;
+  sp->axis_table.resize(D);
+  sp->lam.resize(D);
+  for (int d = 0; d < D; ++d) {
+    sp->axis_table[d] = table_for(pl, g->bc[d][0], g->grid[d], g->n[d], &st);
+    if (st != MPOIS_OK) return st;
+    std::vector<double> lam(size_t(g->n[d]));
+    axis_eigs(g->bc[d][0], g->grid[d], pl->approx, g->n[d], g->h[d], lam.data());
+    for (auto& v : lam) v /= c;
+    st = pl->f64work ? upload_lam<double>(pl, &sp->lam[d], lam) : upload_lam<float>(pl, &sp->lam[d], lam);
+    if (st != MPOIS_OK) return st;
+  }
+  // passes (input and output pointers are filled at execute time)
+  auto axis_pass = [&](int d, bool fused, bool inverse) {
+    Pass p;
+    const AxisTables& at = pl->tables[sp->axis_table[d]];
+    PassArgs& a = p.args;
+    a.ax = at.dev;
+    int64_t inner = 1;
+    for (int e = d + 1; e < D; ++e) inner *= g->n[e];
+    a.nlines = 1;
+    for (int e = 0; e < D; ++e)
+      if (e != d) a.nlines *= g->n[e];
+    a.inner = inner;
+    a.kind_f = inverse ? at.shape.kind_b : at.shape.kind_f;
+    a.kind_b = fused ? at.shape.kind_b : -1;
+    a.singular = sp->singular ? 1 : 0;
+    if (fused) {
+      a.lam_this = sp->lam[d].p;
+      if (D >= 2) a.lam_a = sp->lam[1].p;
+      if (D == 3) {
+        a.lam_b = sp->lam[2].p;
+        a.nb = g->n[2];
+      }
+    }
+    p.axis = d;
+    p.cfg = default_cfg(pl->f64work, int(g->n[d]), int(at.shape.P));
+    if (tune_enabled(pl->flags)) p.cfg = tuned_cfg(p.cfg, pl->f64work, int(g->n[d]), int(at.shape.P), inner == 1);
+    return p;
+  };
+  for (int d = D - 1; d >= 1; --d) sp->passes.push_back(axis_pass(d, false, false));
+  sp->passes.push_back(axis_pass(0, true, false));
+  for (int d = 1; d < D; ++d) sp->passes.push_back(axis_pass(d, false, true));
+  for (const Pass& p : sp->passes)
+    if (p.cfg < 0) return MPOIS_ERR_UNSUPPORTED;
+  // residual description
+  ResidArgs& r = sp->resid;
+  for (int e = 0; e < 3; ++e) {
+    r.n[e] = sp->n[e];
+    const bool real_axis = e >= 3 - D;
+    r.clo[e] = real_axis ? closure_of(sp->bc[e], sp->grid[e]) : C_NONE;
+    r.inv_h2[e] = real_axis ? 1.0 / (sp->h[e] * sp->h[e]) : 0.0;
+  }
+  return MPOIS_OK;
+}
+
+void free_plan(mpois_plan_s* pl) {
+  for (auto& t : pl->tables) {
+    dev_free(&t.tw);
+    dev_free(&t.pre);
+    dev_free(&t.chirp);
+    dev_free(&t.bhat);
+    dev_free(&t.cs);
+    dev_free(&t.stages);
+  }
+  for (auto& s : pl->subs)
+    for (auto& b : s.lam) dev_free(&b);
+  dev_free(&pl->work);
+  dev_free(&pl->partials);
+  dev_free(&pl->scalars);
+  for (auto& r : pl->prof) (void)hipEventDestroy(r.end);
+  if (pl->prof_start) (void)hipEventDestroy(pl->prof_start);
+  if (pl->graph.exec) (void)hipGraphExecDestroy(pl->graph.exec);
+  if (pl->graph.graph) (void)hipGraphDestroy(pl->graph.graph);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  delete pl;
+}
+
+mpois_status create_common(const mpois_grid_desc* gs, int count, int approx, int prec, double rtol, int max_iter,
+                           unsigned flags, mpois_plan* out) {
+  if (!out || !gs || count < 1 || count > 2048) return MPOIS_ERR_INVALID;
+  if (!(std::isfinite(rtol) && rtol >= 0)) return MPOIS_ERR_INVALID;
+  int64_t maxpts = 0;
+  for (int i = 0; i < count; ++i) {
+    mpois_status st = validate_one(&gs[i], approx, prec, max_iter);
+    if (st != MPOIS_OK) return st;
+    if (gs[i].ndim != gs[0].ndim) return MPOIS_ERR_INVALID;
+  }
+  int dev = 0;
+  mpois_status st = device_ready(&dev);
+  if (st != MPOIS_OK) return st;
+  mpois_plan_s* pl = new (std::nothrow) mpois_plan_s();
+  if (!pl) return MPOIS_ERR_NOMEM;
+  pl->approx = approx;
+  pl->prec = prec;
+  pl->rtol = rtol;
+  pl->max_iter = prec == MPOIS_F32_REFINE ? max_iter : 0;
+  pl->flags = flags;
+  pl->device = dev;
+  pl->f64work = prec == MPOIS_F64;
+  pl->subs.resize(size_t(count));
+  for (int i = 0; i < count && st == MPOIS_OK; ++i) {
+    st = build_sub(pl, &gs[i], &pl->subs[i]);
+    maxpts = std::max(maxpts, pl->subs[i].npts);
+  }
+  if (st == MPOIS_OK && prec == MPOIS_F32_REFINE) st = dev_alloc(pl, &pl->work, size_t(maxpts) * sizeof(float));
+  if (st == MPOIS_OK) st = dev_alloc(pl, &pl->partials, size_t(kMaxResidBlocks) * 4 * sizeof(double));
+  if (st == MPOIS_OK) st = dev_alloc(pl, &pl->scalars, size_t(count) * S_COUNT * sizeof(double));
+  if (st == MPOIS_OK && (flags & MPOIS_FLAG_GRAPH)) {
+    if (hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) != hipSuccess) st = MPOIS_ERR_DEVICE;
+  }
+  if (st != MPOIS_OK) {
+    free_plan(pl);
+    return st;
+  }
+  *out = pl;
+  return MPOIS_OK;
+}
+
+// ---------------------------------------------------------------------------- execution
+void prof_mark(mpois_plan_s* pl, int kernel, double bytes, hipStream_t s) {
+  if (!pl->profiling) return;
+  if (pl->prof_used == pl->prof.size()) {
+    ProfRec r{};
+    if (hipEventCreate(&r.end) != hipSuccess) return;
+    pl->prof.push_back(r);
+  }
+  ProfRec& r = pl->prof[pl->prof_used++];
+  r.kernel = kernel;
+  r.bytes = bytes;
+  (void)hipEventRecord(r.end, s);
+}
+
+hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, void* out, int out_f64, void* work,
+                     int work_f64, bool update, const double* shift, hipStream_t s) {
+  const size_t np = sp.passes.size();
+  for (size_t i = 0; i < np; ++i) {
+    Pass& p = sp.passes[i];
+    PassArgs a = p.args;
+    a.src = i == 0 ? in : work;
+    a.src_f64 = i == 0 ? in_f64 : work_f64;
+    const bool last = i + 1 == np;
+    a.dst = last ? out : work;
+    a.dst_f64 = last ? out_f64 : work_f64;
+    a.update = (last && update) ? 1 : 0;
+    a.shift = shift;
+    hipError_t e = launch_line_pass(p.cfg, a, s);
+    if (e != hipSuccess) return e;
+    const double pts = double(sp.npts);
+    prof_mark(pl, p.cfg, pts * ((a.src_f64 ? 8 : 4) + (a.dst_f64 ? 8 : 4) + (a.update ? 8 : 0)), s);
+  }
+  return hipSuccess;
+}
+
+hipError_t run_resid(mpois_plan_s* pl, SubPlan& sp, const void* rhs, const void* phi, void* r, int r_f64,
+                     const double* mg, double* scalars, hipStream_t s) {
+  ResidArgs a = sp.resid;
+  a.phi = static_cast<const double*>(phi);
+  a.g = static_cast<const double*>(rhs);
+  a.r = r;
+  a.r_f64 = r_f64;
+  a.mg = mg;
+  a.partials = static_cast<double*>(pl->partials.p);
+  hipError_t e = launch_resid(a, s);
+  if (e != hipSuccess) return e;
+  prof_mark(pl, 100, double(sp.npts) * (phi == rhs ? 8 : 16) + (r ? double(sp.npts) * (r_f64 ? 8 : 4) : 0), s);
+  e = launch_finalize(a.partials, resid_blocks(a.n), 1.0 / sp.wsum, scalars, s);
+  if (e != hipSuccess) return e;
+  prof_mark(pl, 101, double(resid_blocks(a.n)) * 32, s);
+  return hipSuccess;
+}
+
+hipError_t enqueue_one(mpois_plan_s* pl, SubPlan& sp, size_t sub_index, const void* rhs, void* phi, hipStream_t s) {
+  if (pl->prec == MPOIS_F64) return run_solve(pl, sp, rhs, 1, phi, 1, phi, 1, false, nullptr, s);
+  if (pl->prec == MPOIS_F32) return run_solve(pl, sp, rhs, 0, phi, 0, phi, 0, false, nullptr, s);
+  // FP32 solve, then fixed number of FP64-residual corrections.
+  double* sc = static_cast<double*>(pl->scalars.p) + sub_index * S_COUNT;
+  void* work = pl->work.p;
+  hipError_t e;
+  if (sp.singular) {
+    // m_g = sum w g / sum w, so the FP32 residual carries no large constant.
+    if ((e = run_resid(pl, sp, rhs, rhs, nullptr, 0, nullptr, sc, s)) != hipSuccess) return e;
+  }
+  if ((e = run_solve(pl, sp, rhs, 1, phi, 1, work, 0, false, nullptr, s)) != hipSuccess) return e;
+  for (int it = 0; it < pl->max_iter; ++it) {
+    // r = g - m_g - L phi (FP64, stored FP32), sum w phi -> gauge shift
+    if ((e = run_resid(pl, sp, rhs, phi, work, 0, sp.singular ? sc + S_MG : nullptr, sc, s)) != hipSuccess) return e;
+    if ((e = run_solve(pl, sp, work, 0, phi, 1, work, 0, true, sc + S_SHIFT, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+// The gauge pass above reuses run_resid with phi = rhs only to get sum w g into
+// S_WG / S_MG; the other sums of that call are not used.
+
+extern "C" {
+
+const char* mpois_status_string(mpois_status s) {
+  switch (s) {
+    case MPOIS_OK: return "ok";
+    case MPOIS_ERR_INVALID: return "invalid argument";
+    case MPOIS_ERR_UNSUPPORTED: return "unsupported";
+    case MPOIS_ERR_NOMEM: return "out of device memory";
+    case MPOIS_ERR_DEVICE: return "device error";
+    case MPOIS_ERR_NOT_CONVERGED: return "refinement did not reach rtol";
+    case MPOIS_ERR_NONFINITE: return "non-finite residual";
+  }
+  return "unknown status";
+}
+
+mpois_status mpois_validate(const mpois_grid_desc* grid, int approx, int prec, int max_iter) {
+  return validate_one(grid, approx, prec, max_iter);
+}
+
+mpois_status mpois_axis_eigenvalues(int bc, int grid, int approx, int64_t n, double h, double* out) {
+  if (!out || n < 1 || bc < 0 || bc > 2 || (grid != 0 && grid != 1) || !(h > 0 && std::isfinite(h)))
+    return MPOIS_ERR_INVALID;
+  if (approx != MPOIS_SPECTRAL && approx != MPOIS_FD2) return MPOIS_ERR_INVALID;
+  if (bc == MPOIS_NEUMANN && grid == MPOIS_VERTEX && n < 2) return MPOIS_ERR_INVALID;
+  axis_eigs(bc, bc == MPOIS_PERIODIC ? MPOIS_VERTEX : grid, approx, n, h, out);
+  return MPOIS_OK;
+}
+
+mpois_status mpois_axis_plan(int bc, int grid, int64_t n, int* kind_fwd, int* kind_bwd, int* M, int* P, int* radices,
+                             int cap, int* nradix) {
+  if (n < 1 || bc < 0 || bc > 2 || (grid != 0 && grid != 1)) return MPOIS_ERR_INVALID;
+  if (bc == MPOIS_NEUMANN && grid == MPOIS_VERTEX && n < 2) return MPOIS_ERR_INVALID;
+  AxisShape s = plan_axis_shape(bc, bc == MPOIS_PERIODIC ? MPOIS_VERTEX : grid, n);
+  if (kind_fwd) *kind_fwd = s.kind_f;
+  if (kind_bwd) *kind_bwd = s.kind_b;
+  if (M) *M = int(s.M);
+  if (P) *P = int(s.P);
+  if (nradix) *nradix = int(s.radices.size());
+  if (radices)
+    for (int i = 0; i < cap && i < int(s.radices.size()); ++i) radices[i] = s.radices[i];
+  return MPOIS_OK;
+}
+
+mpois_status mpois_plan_create(const mpois_grid_desc* grid, int approx, int prec, double rtol, int max_iter,
+                               unsigned flags, mpois_plan* out) {
+  return create_common(grid, 1, approx, prec, rtol, max_iter, flags, out);
+}
+
+mpois_status mpois_plan_create_batch(const mpois_grid_desc* grids, int count, int approx, int prec, double rtol,
+                                     int max_iter, unsigned flags, mpois_plan* out) {
+  return create_common(grids, count, approx, prec, rtol, max_iter, flags, out);
+}
+
+static mpois_status check_ptrs(const mpois_plan_s* pl, const SubPlan& sp, const void* rhs, void* phi) {
+  if (!rhs || !phi) return MPOIS_ERR_INVALID;
+  const size_t es = pl->prec == MPOIS_F32 ? 4 : 8;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(rhs), b0 = reinterpret_cast<uintptr_t>(phi);
+  const uintptr_t len = uintptr_t(sp.npts) * es;
+  if (a0 != b0 && a0 < b0 + len && b0 < a0 + len) return MPOIS_ERR_INVALID;
+  if (a0 == b0 && pl->prec == MPOIS_F32_REFINE) return MPOIS_ERR_INVALID;
+  for (const void* p : {rhs, static_cast<const void*>(phi)}) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+      (void)hipGetLastError();
+      return MPOIS_ERR_INVALID;
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) return MPOIS_ERR_INVALID;
+  }
+  return MPOIS_OK;
+}
+
+mpois_status mpois_execute(mpois_plan pl, const void* rhs, void* phi, void* stream) {
+  if (!pl || pl->subs.size() != 1) return MPOIS_ERR_INVALID;
+  SubPlan& sp = pl->subs[0];
+  mpois_status st = check_ptrs(pl, sp, rhs, phi);
+  if (st != MPOIS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  pl->last_rhs = rhs;
+  pl->last_phi = phi;
+  pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
+  if (pl->flags & MPOIS_FLAG_PROFILE) {
+    if (!pl->prof_start && hipEventCreate(&pl->prof_start) != hipSuccess) return MPOIS_ERR_DEVICE;
+    pl->prof_used = 0;
+    pl->profiling = true;
+    (void)hipEventRecord(pl->prof_start, s);
+    const hipError_t e = enqueue_one(pl, sp, 0, rhs, phi, s);
+    pl->profiling = false;
+    return e == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
+  }
+  if (pl->flags & MPOIS_FLAG_GRAPH) {
+    Graph& g = pl->graph;
+    if (!(g.exec && g.rhs == rhs && g.phi == phi)) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+      g.exec = nullptr;
+      g.graph = nullptr;
+      if (hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPOIS_ERR_DEVICE;
+      hipError_t e = enqueue_one(pl, sp, 0, rhs, phi, pl->cap_stream);
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(pl->cap_stream, &graph);
+      if (e != hipSuccess || e2 != hipSuccess || !graph) return MPOIS_ERR_DEVICE;
+      g.graph = graph;
+      if (hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) return MPOIS_ERR_DEVICE;
+      g.rhs = rhs;
+      g.phi = phi;
+    }
+    return hipGraphLaunch(g.exec, s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
+  }
+  return enqueue_one(pl, sp, 0, rhs, phi, s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
+}
+
+mpois_status mpois_execute_batch(mpois_plan pl, const void* const* rhs, void* const* phi, void* stream) {
+  if (!pl || !rhs || !phi) return MPOIS_ERR_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t count = pl->subs.size();
+  for (size_t i = 0; i < count; ++i) {
+    mpois_status st = check_ptrs(pl, pl->subs[i], rhs[i], phi[i]);
+    if (st != MPOIS_OK) return st;
+  }
+  pl->last_rhs_b.assign(rhs, rhs + count);
+  pl->last_phi_b.assign(phi, phi + count);
+  pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
+  for (size_t i = 0; i < count; ++i)
+    if (enqueue_one(pl, pl->subs[i], i, rhs[i], phi[i], s) != hipSuccess) return MPOIS_ERR_DEVICE;
+  return MPOIS_OK;
+}
+
+mpois_status mpois_get_info(mpois_plan pl, void* stream, mpois_info* out) {
+  if (!pl || !out) return MPOIS_ERR_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mpois_info info{};
+  info.iters = pl->last_iters;
+  info.rel_resid = std::nan("");
+  info.zero_mode_rhs = 0.0;
+  const bool batch = !pl->last_rhs_b.empty();
+  const size_t count = batch ? pl->subs.size() : 1;
+  if (!batch && !pl->last_rhs) return MPOIS_ERR_INVALID;
+  if (pl->approx == MPOIS_FD2 && pl->prec != MPOIS_F32) {
+    double worst = 0.0;
+    double mg_worst = 0.0;
+    for (size_t i = 0; i < count; ++i) {
+      SubPlan& sp = pl->subs[i];
+      const void* rhs = batch ? pl->last_rhs_b[i] : pl->last_rhs;
+      const void* phi = batch ? pl->last_phi_b[i] : pl->last_phi;
+      double* sc = static_cast<double*>(pl->scalars.p) + i * S_COUNT;
+      if (sp.singular && run_resid(pl, sp, rhs, phi, nullptr, 0, nullptr, sc, s) != hipSuccess) return MPOIS_ERR_DEVICE;
+      if (run_resid(pl, sp, rhs, phi, nullptr, 0, sp.singular ? sc + S_MG : nullptr, sc, s) != hipSuccess)
+        return MPOIS_ERR_DEVICE;
+      double host[S_COUNT];
+      if (hipMemcpyAsync(host, sc, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess) return MPOIS_ERR_DEVICE;
+      if (hipStreamSynchronize(s) != hipSuccess) return MPOIS_ERR_DEVICE;
+      const double rel = std::sqrt(host[S_R2]) / std::max(std::sqrt(host[S_G2]), 1e-300);
+      const double mg = host[S_MG];
+      if (i == 0 || !(rel <= worst)) {
+        worst = rel;
+        mg_worst = sp.singular ? mg : 0.0;
+      }
+    }
+    info.rel_resid = worst;
+    info.zero_mode_rhs = mg_worst;
+  } else if (hipStreamSynchronize(s) != hipSuccess) {
+    return MPOIS_ERR_DEVICE;
+  }
+  *out = info;
+  if (!std::isfinite(info.rel_resid) && pl->approx == MPOIS_FD2 && pl->prec != MPOIS_F32) return MPOIS_ERR_NONFINITE;
+  if (pl->rtol > 0 && pl->approx == MPOIS_FD2 && info.rel_resid > pl->rtol) return MPOIS_ERR_NOT_CONVERGED;
+  return MPOIS_OK;
+}
+
+mpois_status mpois_destroy(mpois_plan pl) {
+  if (!pl) return MPOIS_OK;
+  free_plan(pl);
+  return MPOIS_OK;
+}
+
+size_t mpois_workspace_bytes(mpois_plan pl) { return pl ? pl->bytes : 0; }
+
+mpois_status mpois_profile(mpois_plan pl, void* stream, int cap, double* ms, double* bytes, int* kernel, int* count) {
+  if (!pl || !count || cap < 0) return MPOIS_ERR_INVALID;
+  if (!(pl->flags & MPOIS_FLAG_PROFILE)) return MPOIS_ERR_INVALID;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return MPOIS_ERR_DEVICE;
+  hipEvent_t prev = pl->prof_start;
+  const int n = int(pl->prof_used);
+  for (int i = 0; i < n && i < cap; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, prev, pl->prof[i].end) != hipSuccess) return MPOIS_ERR_DEVICE;
+    if (ms) ms[i] = double(t);
+    if (bytes) bytes[i] = pl->prof[i].bytes;
+    if (kernel) kernel[i] = pl->prof[i].kernel;
+    prev = pl->prof[i].end;
+  }
+  *count = n;
+  return MPOIS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared
+symbol, validates descriptors, and its host-side tables match the oracle.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpois.h")
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import paper_1409_8116_amd as m
+    if not os.path.exists(m.library_path()):
+        pytest.skip("libmpois.so not built")
+    m.load_library()
+    return m
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:mpois_status|size_t|const char\*)\s+(mpois_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(mp):
+    names = declared_functions()
+    assert len(names) >= 11
+    lib = ctypes.CDLL(mp.library_path())
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(mp):
+    lib = mp.load_library()
+    for code in range(7):
+        assert lib.mpois_status_string(code)
+
+
+def _desc(mp, shape, bc, grid, h=None):
+    return mp.make_desc(shape, h or [0.1] * len(shape), bc, grid)
+
+
+def test_validation(mp):
+    lib = mp.load_library()
+    ok = _desc(mp, (8, 9, 10), ("P", "D", "N"), ("v", "s", "v"))
+    assert lib.mpois_validate(ctypes.byref(ok), 1, 0, 1) == 0
+    assert lib.mpois_validate(None, 1, 0, 1) == 1
+    bad_ndim = _desc(mp, (8,), ("P",), ("v",))
+    bad_ndim.ndim = 4
+    assert lib.mpois_validate(ctypes.byref(bad_ndim), 1, 0, 1) == 1
+    zero_n = _desc(mp, (0, 4), ("P", "P"), ("v", "v"))
+    assert lib.mpois_validate(ctypes.byref(zero_n), 1, 0, 1) == 1
+    nv1 = _desc(mp, (1,), ("N",), ("v",))
+    assert lib.mpois_validate(ctypes.byref(nv1), 1, 0, 1) == 1
+    for hbad in (0.0, -1.0, float("nan"), float("inf")):
+        d = _desc(mp, (4,), ("D",), ("v",), h=[hbad])
+        assert lib.mpois_validate(ctypes.byref(d), 1, 0, 1) == 1
+    half_periodic = _desc(mp, (4,), [("P", "D")], ("v",))
+    assert lib.mpois_validate(ctypes.byref(half_periodic), 1, 0, 1) == 1
+    mixed_dn = _desc(mp, (4,), [("D", "N")], ("v",))
+    assert lib.mpois_validate(ctypes.byref(mixed_dn), 1, 0, 1) == 2
+    # spectral with refinement is not provided
+    assert lib.mpois_validate(ctypes.byref(ok), 0, 2, 1) == 2
+    assert lib.mpois_validate(ctypes.byref(ok), 1, 2, 0) == 1
+    assert lib.mpois_validate(ctypes.byref(ok), 7, 0, 1) == 1
+    assert lib.mpois_validate(ctypes.byref(ok), 1, 9, 1) == 1
+
+
+def test_destroy_null_and_workspace_null(mp):
+    lib = mp.load_library()
+    assert lib.mpois_destroy(None) == 0
+    assert lib.mpois_workspace_bytes(None) == 0
+
+
+def test_plan_without_device_reports_device_error(mp):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = mp.load_library()
+    d = _desc(mp, (8, 8), ("P", "P"), ("v", "v"))
+    h = ctypes.c_void_p()
+    assert lib.mpois_plan_create(ctypes.byref(d), 1, 0, 0.0, 1, 0, ctypes.byref(h)) == 4
+    assert not h.value
+
+
+@pytest.mark.parametrize("bc,grid", [("P", "v"), ("D", "v"), ("D", "s"), ("N", "v"), ("N", "s")])
+@pytest.mark.parametrize("approx", ["fd", "ps"])
+def test_axis_eigenvalues_match_oracle(mp, bc, grid, approx):
+    for n in (2, 3, 7, 16, 33, 511, 512, 1021):
+        h = 1.0 / (n + 3)
+        lib_vals = mp.axis_eigenvalues(bc, grid, approx, n, h)
+        ref = oracle.eigenvalues(bc, grid, n, h, approx)
+        assert np.allclose(lib_vals, ref, rtol=1e-14, atol=0), (n,)
+
+
+def test_axis_plans(mp):
+    p = mp.axis_plan("N", "v", 512)
+    assert (p["forward"], p["backward"], p["M"]) == ("DCT-I", "DCT-I", 1022)
+    p = mp.axis_plan("D", "s", 256)
+    assert (p["forward"], p["backward"], p["M"], p["P"]) == ("DST-II", "DST-III", 256, 256)
+    assert np.prod(p["radices"]) == 256
+    p = mp.axis_plan("D", "v", 100)
+    assert (p["forward"], p["M"]) == ("DST-I", 202)
+    p = mp.axis_plan("P", "v", 1021)  # prime: chirp convolution
+    assert p["P"] >= 2 * 1021 - 1 and p["P"] & (p["P"] - 1) == 0
+    for n in range(1, 300):
+        for bc, grid in (("P", "v"), ("N", "s"), ("D", "v")):
+            q = mp.axis_plan(bc, grid, n)
+            assert int(np.prod(q["radices"])) == q["P"]
+            assert q["P"] == q["M"] or q["P"] >= 2 * q["M"] - 1
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import paper_1409_8116_amd as m
+    monkeypatch.setattr(m, "_lib", None)
+    monkeypatch.setattr(m, "_HERE", str(tmp_path))
+    with pytest.raises(RuntimeError):
+        m.load_library()

@@ -1,0 +1,169 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Error metric: ||phi_gpu - phi_oracle||_2 / ||phi_oracle||_2 over the grid, both
+in the zero-weighted-mean gauge.  Bars: 1e-12 for FP64 and for FP32 with FP64
+refinement, 1e-5 for single-pass FP32.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32r": 1e-12}
+KINDS = [("P", "v"), ("D", "v"), ("D", "s"), ("N", "v"), ("N", "s")]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1409_8116_amd as mp
+    mp.load_library()
+    yield
+
+
+def _mp():
+    import paper_1409_8116_amd as mp
+    return mp
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_solve(g, shape, h, bc, grid, approx, prec, max_iter=2, graph=False, tune=False):
+    mp = _mp()
+    plan = mp.Plan(shape, h, bc, grid, approx=approx, prec=prec, max_iter=max_iter, graph=graph, tune=tune)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    rhs = torch.as_tensor(np.ascontiguousarray(g), dtype=dt).cuda()
+    phi = torch.empty_like(rhs)
+    plan.solve(rhs, phi)
+    torch.cuda.synchronize()
+    out = phi.double().cpu().numpy()
+    info = plan.info()
+    plan.close()
+    return out, info
+
+
+def oracle_solve(g, shape, h, bc, grid, approx):
+    axes = oracle.axes_from(shape, h, bc, grid)
+    return oracle.solve(g, axes, approx)
+
+
+def check(shape, kinds, approx, prec, seed=0, h=None, max_iter=2):
+    bc = tuple(k[0] for k in kinds)
+    grid = tuple(k[1] for k in kinds)
+    h = h or tuple(1.0 / (n + 1) for n in shape)
+    print(f"[parity] shape={shape} kinds={kinds} approx={approx} prec={prec} seed={seed}", flush=True)
+    g = np.random.default_rng(seed).standard_normal(shape)
+    ref = oracle_solve(g, shape, h, bc, grid, approx)
+    out, info = gpu_solve(g, shape, h, bc, grid, approx, prec, max_iter=max_iter)
+    err = rel_err(out, ref)
+    assert err <= TOL[prec], (shape, kinds, approx, prec, err)
+    return err, info
+
+
+# ------------------------------------------------------------------ 1D: every kind, many lengths
+LENGTHS = [1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 12, 13, 16, 17, 25, 31, 32, 37, 49, 64, 100, 121, 127, 128, 143, 169,
+           255, 256, 257, 343, 509, 511, 512, 513, 1000, 1021, 1024]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_1d_all_lengths(kind, prec):
+    for n in LENGTHS:
+        if kind == ("N", "v") and n < 2:
+            continue
+        for approx in ("fd", "ps"):
+            check((n,), [kind], approx, prec, seed=n)
+
+
+# ------------------------------------------------------------------ 2D / 3D: every kind pair, ragged tiles
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_2d_all_kind_pairs(prec):
+    for k0, k1 in itertools.product(KINDS, repeat=2):
+        check((37, 45), [k0, k1], "fd", prec, seed=3)
+        check((20, 33), [k0, k1], "ps", prec, seed=4)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_3d_mixed_kinds(prec):
+    combos = [[("P", "v"), ("D", "s"), ("N", "s")], [("N", "v")] * 3, [("D", "v"), ("P", "v"), ("N", "v")],
+              [("P", "v")] * 3, [("D", "s"), ("N", "v"), ("P", "v")], [("N", "s"), ("D", "v"), ("D", "s")]]
+    for kinds in combos:
+        for approx in ("fd", "ps"):
+            check((19, 24, 35), kinds, approx, prec, seed=5)
+
+
+def test_3d_several_tiles_and_tails():
+    # lines per tile are 16-32; these shapes leave partial tiles on every axis
+    for shape in [(33, 17, 65), (3, 50, 7), (1, 1, 40), (40, 1, 1), (2, 2, 2)]:
+        for kinds in ([("P", "v"), ("D", "s"), ("N", "s")], [("N", "v"), ("N", "v"), ("D", "v")]):
+            check(shape, kinds, "fd", "f64", seed=6)
+            check(shape, kinds, "fd", "f32", seed=6)
+
+
+# ------------------------------------------------------------------ refinement
+@pytest.mark.parametrize("kinds", [[("N", "v")] * 3, [("P", "v")] * 3, [("P", "v"), ("D", "s"), ("N", "s")],
+                                   [("D", "v"), ("N", "s"), ("P", "v")]])
+def test_refinement_reaches_fp64(kinds):
+    err, info = check((24, 31, 20), kinds, "fd", "f32r", seed=7, max_iter=2)
+    assert info["iters"] == 3
+    assert info["rel_resid"] < 1e-11
+
+
+def test_refinement_2d_1d():
+    check((45, 64), [("N", "v"), ("P", "v")], "fd", "f32r", seed=8, max_iter=2)
+    check((200,), [("N", "s")], "fd", "f32r", seed=9, max_iter=2)
+    check((201,), [("D", "v")], "fd", "f32r", seed=10, max_iter=2)
+
+
+def test_refinement_incompatible_rhs_is_projected():
+    """A right-hand side with a large mean on a singular problem: solved for g - m_g."""
+    shape = (20, 18, 22)
+    kinds = [("N", "v"), ("N", "s"), ("P", "v")]
+    bc = tuple(k[0] for k in kinds)
+    grid = tuple(k[1] for k in kinds)
+    h = (0.05, 0.05, 0.05)
+    g = np.random.default_rng(1).standard_normal(shape) + 5.0
+    ref = oracle_solve(g, shape, h, bc, grid, "fd")
+    out, info = gpu_solve(g, shape, h, bc, grid, "fd", "f32r", max_iter=2)
+    assert rel_err(out, ref) <= 1e-12
+    axes = oracle.axes_from(shape, h, bc, grid)
+    assert abs(info["zero_mode_rhs"] - oracle.weighted_mean(g, axes)) <= 1e-12 * 5
+
+
+# ------------------------------------------------------------------ configurations at full size
+def test_periodic_box_32():
+    d, g = workloads.periodic_noise(32, seed=1)
+    ref = oracle_solve(g, d["shape"], d["h"], d["bc"], d["grid"], d["approx"])
+    out, _ = gpu_solve(g, d["shape"], d["h"], d["bc"], d["grid"], d["approx"], "f64")
+    assert rel_err(out, ref) <= 1e-12
+    assert abs(out.mean()) <= 1e-14 * np.abs(out).max()
+
+
+@pytest.mark.parametrize("approx,prec", [("fd", "f64"), ("ps", "f64"), ("fd", "f32"), ("ps", "f32")])
+def test_mixed_box_256(approx, prec):
+    d, g, modes = workloads.mixed_modes(256, seed=2, approx=approx)
+    ref = oracle_solve(g, d["shape"], d["h"], d["bc"], d["grid"], approx)
+    out, _ = gpu_solve(g, d["shape"], d["h"], d["bc"], d["grid"], approx, prec)
+    assert rel_err(out, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec,max_iter", [("f64", 0), ("f32r", 2)])
+def test_neumann_cube_512(prec, max_iter):
+    d, g = workloads.neumann_blobs(512, seed=3)
+    axes = oracle.axes_from(d["shape"], d["h"], d["bc"], d["grid"])
+    ref = oracle.solve(g, axes, "fd")
+    out, info = gpu_solve(g, d["shape"], d["h"], d["bc"], d["grid"], "fd", prec, max_iter=max(max_iter, 1))
+    err = rel_err(out, ref)
+    print(f"[parity] neumann cube 512 {prec}: rel err {err:.3e} resid {info['rel_resid']:.3e}", flush=True)
+    assert err <= 1e-12
