@@ -55,7 +55,7 @@ struct PassArgs {
   int kind_b;           // transform applied after the eigenvalue scaling; -1 = none
   int update;           // 1: dst <- dst + result - shift[0]  (dst is double)
   int singular;         // 1: the all-zero mode gets coefficient 0
-  const double* shift;  // device scalar for update mode
+  const double* shift;  // device scalar subtracted in update mode, or null
   const void* lam_this; // scaled eigenvalues along this axis (working precision)
   const void* lam_a;    // scaled eigenvalues of the other axes, or null
   const void* lam_b;

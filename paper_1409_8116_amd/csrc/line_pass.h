@@ -411,7 +411,8 @@ __device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const TileGeom& g, cons
   const int tid = opaque_tid();
   const int t = tid % TL;  // fixed per thread
   T lam_other = T(0);
-  bool zero_line = false;
+  bool zero_line = false;  // the all-zero mode of a singular problem lives on line 0
+  bool dead_line = false;  // padding line of a partial tile: holds zeros, must stay finite
   if (scale) {
     const int64_t l = l0 + t;
     const T* la = static_cast<const T*>(a.lam_a);
@@ -419,6 +420,8 @@ __device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const TileGeom& g, cons
     if (l < a.nlines) {
       if (lb) lam_other = la[l / a.nb] + lb[l % a.nb];
       else if (la) lam_other = la[l];
+    } else {
+      dead_line = true;
     }
     zero_line = a.singular && (l == 0);
   }
@@ -432,7 +435,7 @@ __device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const TileGeom& g, cons
       T x = unpack_value<T, NP, kind>(Z, ax, t, k);
       if (scale) {
         const T lam = lam_other + lt[k];
-        x = (zero_line && k == 0) ? T(0) : x / lam;
+        x = (dead_line || (zero_line && k == 0)) ? T(0) : x / lam;
       }
       v[i] = x;
     }
@@ -529,7 +532,7 @@ __global__ void __launch_bounds__(NT) line_pass(PassArgs a) {
       const T x = X[t * g.pitch + j];
       if (a.update) {
         double* d = static_cast<double*>(a.dst);
-        d[base + f] = d[base + f] + double(x) - a.shift[0];
+        d[base + f] = d[base + f] + double(x) - (a.shift ? a.shift[0] : 0.0);
       } else if (a.dst_f64) {
         static_cast<double*>(a.dst)[base + f] = double(x);
       } else {
@@ -546,7 +549,7 @@ __global__ void __launch_bounds__(NT) line_pass(PassArgs a) {
         const int64_t o = base + int64_t(j) * B;
         if (a.update) {
           double* d = static_cast<double*>(a.dst);
-          d[o] = d[o] + double(x) - a.shift[0];
+          d[o] = d[o] + double(x) - (a.shift ? a.shift[0] : 0.0);
         } else if (a.dst_f64) {
           static_cast<double*>(a.dst)[o] = double(x);
         } else {

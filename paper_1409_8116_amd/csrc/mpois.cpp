@@ -667,7 +667,9 @@ hipError_t enqueue_one(mpois_plan_s* pl, SubPlan& sp, size_t sub_index, const vo
   for (int it = 0; it < pl->max_iter; ++it) {
     // r = g - m_g - L phi (FP64, stored FP32), sum w phi -> gauge shift
     if ((e = run_resid(pl, sp, rhs, phi, work, 0, sp.singular ? sc + S_MG : nullptr, sc, s)) != hipSuccess) return e;
-    if ((e = run_solve(pl, sp, work, 0, phi, 1, work, 0, true, sc + S_SHIFT, s)) != hipSuccess) return e;
+    // phi <- phi + delta, minus the weighted mean of phi when the problem is singular
+    if ((e = run_solve(pl, sp, work, 0, phi, 1, work, 0, true, sp.singular ? sc + S_SHIFT : nullptr, s)) != hipSuccess)
+      return e;
   }
   return hipSuccess;
 }
