@@ -46,12 +46,14 @@ __device__ __forceinline__ double second_diff(const double* __restrict__ phi, in
 
 constexpr int RESID_NT = 256;
 
-__global__ void __launch_bounds__(RESID_NT) resid_kernel(ResidArgs a) {
+// Block `blk` of `nblk` blocks over one grid: rows are (i0, i1) pairs, threads
+// run along the contiguous axis.  Writes the 4 block partial sums to part[0..3].
+__device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int64_t nblk, double* part) {
   const int64_t n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
   const int64_t rows = n0 * n1;
   const double mg = a.mg ? a.mg[0] : 0.0;
   double s_wphi = 0.0, s_wg = 0.0, s_r2 = 0.0, s_g2 = 0.0;
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+  for (int64_t row = blk; row < rows; row += nblk) {
     const int64_t i0 = row / n1, i1 = row - i0 * n1;
     const double w01 = axis_weight(a.clo[0], i0, n0) * axis_weight(a.clo[1], i1, n1);
     for (int64_t i2 = threadIdx.x; i2 < n2; i2 += RESID_NT) {
@@ -85,16 +87,33 @@ __global__ void __launch_bounds__(RESID_NT) resid_kernel(ResidArgs a) {
       for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x < 4) a.partials[int64_t(blockIdx.x) * 4 + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 4) part[threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Sum the block partials in a fixed order; derive the gauge shift and the mean of g.
-__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ partials, int nblocks,
-                                                       double inv_wsum, double* __restrict__ scalars) {
+__global__ void __launch_bounds__(RESID_NT) resid_kernel(ResidArgs a) {
+  resid_body(a, blockIdx.x, gridDim.x, a.partials + int64_t(blockIdx.x) * 4);
+}
+
+__global__ void __launch_bounds__(RESID_NT) resid_batch_kernel(BatchResidArgs b) {
+  const int pi = b.blk_prob[blockIdx.x];
+  ResidArgs a = b.args[pi];
+  a.phi = static_cast<const double*>(b.phi_tab[pi]);
+  a.g = static_cast<const double*>(b.g_tab[pi]);
+  a.r = b.r_tab ? b.r_tab[pi] : nullptr;
+  a.r_f64 = b.r_f64;
+  a.mg = (b.use_mg && a.singular) ? b.scalars + int64_t(pi) * S_COUNT + S_MG : nullptr;
+  const int blk = int(blockIdx.x) - b.blk_start[pi];
+  resid_body(a, blk, b.blk_count[pi], b.partials + int64_t(blockIdx.x) * 4);
+}
+
+// Sum block partials [first, first + count) in a fixed order and derive the
+// gauge shift and the weighted mean of g.
+__device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int first, int count,
+                                              double inv_wsum, double* __restrict__ scalars) {
   __shared__ double red[4][256];
   double s[4] = {0, 0, 0, 0};
-  for (int b = threadIdx.x; b < nblocks; b += 256)
-    for (int q = 0; q < 4; ++q) s[q] += partials[int64_t(b) * 4 + q];
+  for (int b = threadIdx.x; b < count; b += 256)
+    for (int q = 0; q < 4; ++q) s[q] += partials[int64_t(first + b) * 4 + q];
   for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = s[q];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
@@ -110,6 +129,21 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict_
     scalars[S_SHIFT] = red[0][0] * inv_wsum;
     scalars[S_MG] = red[1][0] * inv_wsum;
   }
+}
+
+__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ partials, int nblocks,
+                                                       double inv_wsum, double* __restrict__ scalars) {
+  finalize_body(partials, 0, nblocks, inv_wsum, scalars);
+}
+
+// One block per grid.
+__global__ void __launch_bounds__(256) finalize_batch_kernel(const double* __restrict__ partials,
+                                                             const int* __restrict__ blk_start,
+                                                             const int* __restrict__ blk_count,
+                                                             const double* __restrict__ inv_wsum,
+                                                             double* __restrict__ scalars) {
+  const int pi = blockIdx.x;
+  finalize_body(partials, blk_start[pi], blk_count[pi], inv_wsum[pi], scalars + int64_t(pi) * S_COUNT);
 }
 
 // Fill a double array with zeros (used instead of memset nodes so the sequence is graph-safe).
@@ -131,6 +165,18 @@ hipError_t launch_resid(const ResidArgs& a, hipStream_t s) {
 
 hipError_t launch_finalize(const double* partials, int nblocks, double inv_wsum, double* scalars, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, inv_wsum, scalars);
+  return hipGetLastError();
+}
+
+hipError_t launch_resid_batch(const BatchResidArgs& b, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(resid_batch_kernel, dim3(blocks), dim3(RESID_NT), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const double* partials, const int* blk_start, const int* blk_count,
+                                 const double* inv_wsum, double* scalars, int count, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_batch_kernel, dim3(count), dim3(256), 0, s, partials, blk_start, blk_count, inv_wsum,
+                     scalars);
   return hipGetLastError();
 }
 

@@ -8,6 +8,8 @@ namespace mpois {
 
 hipError_t launch_line_pass_f64(int i, const PassArgs& a, hipStream_t s, size_t lds);
 hipError_t launch_line_pass_f32(int i, const PassArgs& a, hipStream_t s, size_t lds);
+hipError_t launch_line_pass_batch_f64(int i, const BatchPassArgs& b, int blocks, hipStream_t s, size_t lds);
+hipError_t launch_line_pass_batch_f32(int i, const BatchPassArgs& b, int blocks, hipStream_t s, size_t lds);
 hipError_t prepare_line_pass_f64();
 hipError_t prepare_line_pass_f32();
 
@@ -57,6 +59,12 @@ hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s) {
   if (cfg < 0 || cfg >= num_kernel_cfgs()) return hipErrorInvalidValue;
   const size_t lds = line_pass_lds(cfg, a.ax.n, a.ax.P);
   return cfg < kNumF64 ? launch_line_pass_f64(cfg, a, s, lds) : launch_line_pass_f32(cfg - kNumF64, a, s, lds);
+}
+
+hipError_t launch_line_pass_batch(int cfg, const BatchPassArgs& b, int blocks, size_t lds, hipStream_t s) {
+  if (cfg < 0 || cfg >= num_kernel_cfgs()) return hipErrorInvalidValue;
+  return cfg < kNumF64 ? launch_line_pass_batch_f64(cfg, b, blocks, s, lds)
+                       : launch_line_pass_batch_f32(cfg - kNumF64, b, blocks, s, lds);
 }
 
 }  // namespace mpois

@@ -63,6 +63,18 @@ struct PassArgs {
   AxisDev ax;
 };
 
+// One launch of the line-transform kernel over many grids.
+struct BatchPassArgs {
+  const PassArgs* args;       // per-grid pass description (src/dst/update fields ignored)
+  const int* tile_prob;       // per block: grid index
+  const int* tile_idx;        // per block: tile index within that grid
+  const void* const* src_tab; // per-grid source array
+  void* const* dst_tab;       // per-grid destination array
+  int src_f64, dst_f64, update;
+  int shift_stride;           // doubles between consecutive grids' scalars
+  const double* shift_base;   // first grid's gauge shift (singular grids only), or null
+};
+
 // Stencil residual over a (n0, n1, n2) box, all axes described by a closure.
 enum Closure : int { C_NONE = 0, C_PER = 1, C_DV = 2, C_DS = 3, C_NV = 4, C_NS = 5 };
 
@@ -76,6 +88,23 @@ struct ResidArgs {
   double inv_h2[3];
   const double* mg;     // device scalar subtracted from g (or null)
   double* partials;     // 4 per block: sum w phi, sum w g, sum r^2, sum (g-mg)^2
+  int singular;         // every axis periodic or Neumann
+};
+
+// Residual over many grids in one launch: block b handles grid blk_prob[b]
+// as its block (b - blk_start[grid]) of blk_count[grid].
+struct BatchResidArgs {
+  const ResidArgs* args;      // per grid (phi/g/r/mg/partials fields ignored)
+  const int* blk_prob;
+  const int* blk_start;       // per grid: first block
+  const int* blk_count;       // per grid: number of blocks
+  const void* const* phi_tab;
+  const void* const* g_tab;
+  void* const* r_tab;         // or null: no residual output
+  int r_f64;
+  int use_mg;                 // subtract scalars[grid].S_MG from g on singular grids
+  double* scalars;            // S_COUNT per grid
+  double* partials;           // 4 per block
 };
 
 // Reduced scalars kept on the device.

@@ -466,15 +466,14 @@ __device__ __forceinline__ void unpack(cx<T>* Z, T* X, const TileGeom& g, int ki
 }
 
 template <typename T, int NP, int NT, int PMAX>
-__global__ void __launch_bounds__(NT) line_pass(PassArgs a) {
+__device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, unsigned char* smem) {
   constexpr int TL = 2 * NP;
-  extern __shared__ __align__(16) unsigned char smem[];
   T* X = reinterpret_cast<T*>(smem);
   cx<T>* Z = reinterpret_cast<cx<T>*>(smem);
   const AxisDev& ax = a.ax;
   const int n = ax.n;
   const int64_t B = a.inner;
-  const int64_t l0 = int64_t(blockIdx.x) * TL;
+  const int64_t l0 = tile * TL;
   TileGeom g;
   g.contiguous = (B == 1);
   g.pitch = n | 1;
@@ -561,6 +560,30 @@ __global__ void __launch_bounds__(NT) line_pass(PassArgs a) {
 }
 
 
+// One grid: block b owns tile b.
+template <typename T, int NP, int NT, int PMAX>
+__global__ void __launch_bounds__(NT) line_pass(PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  line_pass_body<T, NP, NT, PMAX>(a, int64_t(blockIdx.x), smem);
+}
+
+// Many grids in one launch: block b works on tile tile_idx[b] of grid
+// tile_prob[b]; the per-grid pass description comes from a device table and
+// the array pointers from per-grid pointer tables.
+template <typename T, int NP, int NT, int PMAX>
+__global__ void __launch_bounds__(NT) line_pass_batch(BatchPassArgs b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int pi = b.tile_prob[blockIdx.x];
+  PassArgs a = b.args[pi];
+  a.src = b.src_tab[pi];
+  a.dst = b.dst_tab[pi];
+  a.src_f64 = b.src_f64;
+  a.dst_f64 = b.dst_f64;
+  a.update = b.update;
+  a.shift = (b.update && b.shift_base && a.singular) ? b.shift_base + int64_t(pi) * b.shift_stride : nullptr;
+  line_pass_body<T, NP, NT, PMAX>(a, int64_t(b.tile_idx[blockIdx.x]), smem);
+}
+
 template <typename T, int NP, int NT, int PMAX>
 hipError_t launch_lp(const PassArgs& a, hipStream_t s, size_t lds) {
   constexpr int64_t TL = 2 * NP;
@@ -570,8 +593,17 @@ hipError_t launch_lp(const PassArgs& a, hipStream_t s, size_t lds) {
 }
 
 template <typename T, int NP, int NT, int PMAX>
+hipError_t launch_lp_batch(const BatchPassArgs& b, int blocks, hipStream_t s, size_t lds) {
+  hipLaunchKernelGGL((line_pass_batch<T, NP, NT, PMAX>), dim3(unsigned(blocks)), dim3(NT), lds, s, b);
+  return hipGetLastError();
+}
+
+template <typename T, int NP, int NT, int PMAX>
 hipError_t prepare_lp() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass<T, NP, NT, PMAX>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass<T, NP, NT, PMAX>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass_batch<T, NP, NT, PMAX>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 

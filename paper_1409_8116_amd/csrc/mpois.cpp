@@ -30,6 +30,10 @@ int resid_blocks(const int64_t n[3]);
 hipError_t launch_resid(const ResidArgs& a, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int nblocks, double inv_wsum, double* scalars, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
+hipError_t launch_line_pass_batch(int cfg, const BatchPassArgs& b, int blocks, size_t lds, hipStream_t s);
+hipError_t launch_resid_batch(const BatchResidArgs& b, int blocks, hipStream_t s);
+hipError_t launch_finalize_batch(const double* partials, const int* blk_start, const int* blk_count,
+                                 const double* inv_wsum, double* scalars, int count, hipStream_t s);
 }  // namespace mpois
 
 using namespace mpois;
@@ -124,31 +128,31 @@ bool factor_radices(int64_t M, std::vector<int>* out) {
   return m == 1;
 }
 
-int64_t next_pow2(int64_t x) {
-  int64_t p = 1;
-  while (p < x) p <<= 1;
-  return p;
-}
-
-// Iterative radix-2 FFT (sign -1) in FP64 for the Bluestein kernel spectrum.
-void host_fft(std::vector<std::complex<double>>& a) {
-  const size_t n = a.size();
-  for (size_t i = 1, j = 0; i < n; ++i) {
-    size_t bit = n >> 1;
-    for (; j & bit; bit >>= 1) j ^= bit;
-    j ^= bit;
-    if (i < j) std::swap(a[i], a[j]);
+// Recursive mixed-radix DFT (sign -1) in FP64 for the Bluestein kernel
+// spectrum; lengths factor over the codelet radices.
+void host_dft(std::vector<std::complex<double>>& a) {
+  const int64_t n = int64_t(a.size());
+  if (n <= 1) return;
+  int64_t r = 0;
+  for (int64_t c : {2, 3, 5, 7, 11, 13})
+    if (n % c == 0) { r = c; break; }
+  if (r == 0) {  // not reached for planner lengths; direct sum as a safe fallback
+    std::vector<std::complex<double>> out(static_cast<size_t>(n));
+    for (int64_t k = 0; k < n; ++k)
+      for (int64_t j = 0; j < n; ++j)
+        out[k] += a[j] * std::complex<double>(cospi_frac(2 * j * k, n), -sinpi_frac(2 * j * k, n));
+    a = out;
+    return;
   }
-  for (size_t len = 2; len <= n; len <<= 1) {
-    for (size_t i = 0; i < n; i += len) {
-      for (size_t k = 0; k < len / 2; ++k) {
-        const double ang = -2.0 * M_PI * double(k) / double(len);
-        const std::complex<double> w(std::cos(ang), std::sin(ang));
-        const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
-        a[i + k] = u + v;
-        a[i + k + len / 2] = u - v;
-      }
-    }
+  const int64_t m = n / r;
+  std::vector<std::vector<std::complex<double>>> sub(static_cast<size_t>(r), std::vector<std::complex<double>>(static_cast<size_t>(m)));
+  for (int64_t j = 0; j < m; ++j)
+    for (int64_t q = 0; q < r; ++q) sub[q][j] = a[j * r + q];
+  for (auto& v : sub) host_dft(v);
+  for (int64_t k = 0; k < n; ++k) {
+    std::complex<double> acc = 0;
+    for (int64_t q = 0; q < r; ++q) acc += sub[q][k % m] * std::complex<double>(cospi_frac(2 * q * k, n), -sinpi_frac(2 * q * k, n));
+    a[k] = acc;
   }
 }
 
@@ -166,9 +170,11 @@ AxisShape plan_axis_shape(int bc, int grid, int64_t n) {
   if (factor_radices(s.M, &s.radices)) {
     s.P = s.M;
   } else {
+    // Bluestein: any cyclic-convolution length >= 2M - 1 works; take the
+    // smallest one the codelet radices factor.
     s.bluestein = true;
-    s.P = next_pow2(2 * s.M - 1);
-    factor_radices(s.P, &s.radices);
+    s.P = 2 * s.M - 1;
+    while (!factor_radices(s.P, &s.radices)) ++s.P;
   }
   return s;
 }
@@ -223,6 +229,30 @@ struct ProfRec {
   hipEvent_t end;  // recorded after the launch
 };
 
+// Batched execution: per pass index, one launch per kernel shape over all
+// grids that use it; per-grid descriptions in device tables.
+struct BatchGroup {
+  int cfg = 0;
+  int blocks = 0;
+  size_t lds = 0;
+  DevBuf tile_prob, tile_idx;
+};
+
+struct BatchPass {
+  DevBuf args;  // PassArgs per grid
+  std::vector<BatchGroup> groups;
+};
+
+struct BatchState {
+  std::vector<BatchPass> passes;
+  DevBuf rhs_tab, phi_tab, work_tab;  // per-grid device pointers
+  DevBuf resid_args, blk_prob, blk_start, blk_count, inv_wsum, partials;
+  int resid_blocks = 0;
+  bool any_singular = false;
+  std::vector<const void*> host_rhs;
+  std::vector<void*> host_phi;
+};
+
 struct Graph {
   const void* rhs = nullptr;
   void* phi = nullptr;
@@ -253,6 +283,8 @@ struct mpois_plan_s {
   Graph graph;
   hipStream_t cap_stream = nullptr;
   hipEvent_t prof_start = nullptr;
+  BatchState batch;
+  bool batched = false;
   std::vector<ProfRec> prof;
   size_t prof_used = 0;
   bool profiling = false;
@@ -342,14 +374,14 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
   }
   // Bluestein: chirp w_m = e^{-i pi m^2/M}, kernel b = conj(w) wrapped, its DFT / P.
   if (s.bluestein) {
-    std::vector<std::complex<double>> w(size_t(s.M)), b(size_t(s.P), {0.0, 0.0});
+    std::vector<std::complex<double>> w(static_cast<size_t>(s.M)), b(size_t(s.P), {0.0, 0.0});
     for (int64_t m = 0; m < s.M; ++m) {
       const int64_t q = (m * m) % (2 * s.M);
       w[m] = {cospi_frac(q, s.M), -sinpi_frac(q, s.M)};
     }
     for (int64_t m = 0; m < s.M; ++m) b[m] = std::conj(w[m]);
     for (int64_t m = 1; m < s.M; ++m) b[s.P - m] = std::conj(w[m]);
-    host_fft(b);
+    host_dft(b);
     for (auto& x : b) x /= double(s.P);
     to_prec(w, &h);
     if ((st = dev_upload(pl, &at->chirp, h)) != MPOIS_OK) return st;
@@ -486,7 +518,7 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
   for (int d = 0; d < D; ++d) {
     sp->axis_table[d] = table_for(pl, g->bc[d][0], g->grid[d], g->n[d], &st);
     if (st != MPOIS_OK) return st;
-    std::vector<double> lam(size_t(g->n[d]));
+    std::vector<double> lam(static_cast<size_t>(g->n[d]));
     axis_eigs(g->bc[d][0], g->grid[d], pl->approx, g->n[d], g->h[d], lam.data());
     for (auto& v : lam) v /= c;
     st = pl->f64work ? upload_lam<double>(pl, &sp->lam[d], lam) : upload_lam<float>(pl, &sp->lam[d], lam);
@@ -547,6 +579,17 @@ void free_plan(mpois_plan_s* pl) {
   }
   for (auto& s : pl->subs)
     for (auto& b : s.lam) dev_free(&b);
+  for (auto& bp : pl->batch.passes) {
+    dev_free(&bp.args);
+    for (auto& g : bp.groups) {
+      dev_free(&g.tile_prob);
+      dev_free(&g.tile_idx);
+    }
+  }
+  for (DevBuf* b : {&pl->batch.rhs_tab, &pl->batch.phi_tab, &pl->batch.work_tab, &pl->batch.resid_args,
+                    &pl->batch.blk_prob, &pl->batch.blk_start, &pl->batch.blk_count, &pl->batch.inv_wsum,
+                    &pl->batch.partials})
+    dev_free(b);
   dev_free(&pl->work);
   dev_free(&pl->partials);
   dev_free(&pl->scalars);
@@ -557,6 +600,8 @@ void free_plan(mpois_plan_s* pl) {
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
   delete pl;
 }
+
+mpois_status build_batch(mpois_plan_s* pl);
 
 mpois_status create_common(const mpois_grid_desc* gs, int count, int approx, int prec, double rtol, int max_iter,
                            unsigned flags, mpois_plan* out) {
@@ -585,7 +630,11 @@ mpois_status create_common(const mpois_grid_desc* gs, int count, int approx, int
     st = build_sub(pl, &gs[i], &pl->subs[i]);
     maxpts = std::max(maxpts, pl->subs[i].npts);
   }
-  if (st == MPOIS_OK && prec == MPOIS_F32_REFINE) st = dev_alloc(pl, &pl->work, size_t(maxpts) * sizeof(float));
+  int64_t total_pts = 0;
+  for (auto& sp : pl->subs) total_pts += sp.npts;
+  const int64_t work_pts = count > 1 ? total_pts : maxpts;
+  if (st == MPOIS_OK && prec == MPOIS_F32_REFINE) st = dev_alloc(pl, &pl->work, size_t(work_pts) * sizeof(float));
+  if (st == MPOIS_OK && count > 1) st = build_batch(pl);
   if (st == MPOIS_OK) st = dev_alloc(pl, &pl->partials, size_t(kMaxResidBlocks) * 4 * sizeof(double));
   if (st == MPOIS_OK) st = dev_alloc(pl, &pl->scalars, size_t(count) * S_COUNT * sizeof(double));
   if (st == MPOIS_OK && (flags & MPOIS_FLAG_GRAPH)) {
@@ -669,6 +718,154 @@ hipError_t enqueue_one(mpois_plan_s* pl, SubPlan& sp, size_t sub_index, const vo
     if ((e = run_resid(pl, sp, rhs, phi, work, 0, sp.singular ? sc + S_MG : nullptr, sc, s)) != hipSuccess) return e;
     // phi <- phi + delta, minus the weighted mean of phi when the problem is singular
     if ((e = run_solve(pl, sp, work, 0, phi, 1, work, 0, true, sp.singular ? sc + S_SHIFT : nullptr, s)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+mpois_status build_batch(mpois_plan_s* pl) {
+  BatchState& B = pl->batch;
+  pl->batched = true;
+  const int count = int(pl->subs.size());
+  const size_t npass = pl->subs[0].passes.size();
+  B.passes.resize(npass);
+  for (size_t p = 0; p < npass; ++p) {
+    BatchPass& bp = B.passes[p];
+    std::vector<PassArgs> args(static_cast<size_t>(count));
+    std::map<int, std::pair<std::vector<int>, std::vector<int>>> by_cfg;  // cfg -> (tile_prob, tile_idx)
+    std::map<int, size_t> lds_of;
+    for (int i = 0; i < count; ++i) {
+      const Pass& ps = pl->subs[i].passes[p];
+      args[i] = ps.args;
+      int cf64, np, nt, pmax;
+      kernel_cfg(ps.cfg, &cf64, &np, &nt, &pmax);
+      const int64_t tiles = (ps.args.nlines + 2 * np - 1) / (2 * np);
+      auto& lists = by_cfg[ps.cfg];
+      for (int64_t t = 0; t < tiles; ++t) {
+        lists.first.push_back(i);
+        lists.second.push_back(int(t));
+      }
+      lds_of[ps.cfg] = std::max(lds_of[ps.cfg], line_pass_lds(ps.cfg, ps.args.ax.n, ps.args.ax.P));
+    }
+    mpois_status st = dev_upload(pl, &bp.args, args);
+    if (st != MPOIS_OK) return st;
+    for (auto& kv : by_cfg) {
+      BatchGroup g;
+      g.cfg = kv.first;
+      g.blocks = int(kv.second.first.size());
+      g.lds = lds_of[kv.first];
+      if ((st = dev_upload(pl, &g.tile_prob, kv.second.first)) != MPOIS_OK) return st;
+      if ((st = dev_upload(pl, &g.tile_idx, kv.second.second)) != MPOIS_OK) return st;
+      bp.groups.push_back(g);
+    }
+  }
+  // residual blocks: about 8k points each, 1..256 per grid
+  std::vector<ResidArgs> rargs(static_cast<size_t>(count));
+  std::vector<int> blk_prob, blk_start(static_cast<size_t>(count)), blk_count(static_cast<size_t>(count));
+  std::vector<double> inv_wsum(static_cast<size_t>(count));
+  for (int i = 0; i < count; ++i) {
+    const SubPlan& sp = pl->subs[i];
+    rargs[i] = sp.resid;
+    rargs[i].singular = sp.singular ? 1 : 0;
+    B.any_singular = B.any_singular || sp.singular;
+    const int64_t rows = sp.n[0] * sp.n[1];
+    int64_t nb = (sp.npts + 8191) / 8192;
+    nb = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(nb, 256), rows));
+    blk_start[i] = int(blk_prob.size());
+    blk_count[i] = int(nb);
+    for (int64_t b = 0; b < nb; ++b) blk_prob.push_back(i);
+    inv_wsum[i] = 1.0 / sp.wsum;
+  }
+  B.resid_blocks = int(blk_prob.size());
+  mpois_status st = dev_upload(pl, &B.resid_args, rargs);
+  if (st == MPOIS_OK) st = dev_upload(pl, &B.blk_prob, blk_prob);
+  if (st == MPOIS_OK) st = dev_upload(pl, &B.blk_start, blk_start);
+  if (st == MPOIS_OK) st = dev_upload(pl, &B.blk_count, blk_count);
+  if (st == MPOIS_OK) st = dev_upload(pl, &B.inv_wsum, inv_wsum);
+  if (st == MPOIS_OK) st = dev_alloc(pl, &B.partials, size_t(B.resid_blocks) * 4 * sizeof(double));
+  if (st == MPOIS_OK) st = dev_alloc(pl, &B.rhs_tab, size_t(count) * sizeof(void*));
+  if (st == MPOIS_OK) st = dev_alloc(pl, &B.phi_tab, size_t(count) * sizeof(void*));
+  if (st != MPOIS_OK) return st;
+  if (pl->prec == MPOIS_F32_REFINE) {
+    std::vector<void*> work(static_cast<size_t>(count));
+    int64_t off = 0;
+    for (int i = 0; i < count; ++i) {
+      work[i] = static_cast<float*>(pl->work.p) + off;
+      off += pl->subs[i].npts;
+    }
+    if ((st = dev_upload(pl, &B.work_tab, work)) != MPOIS_OK) return st;
+  }
+  return MPOIS_OK;
+}
+
+// All passes of one solve over every grid of a batch.  src/dst tables per pass:
+// first pass reads `in`, last pass writes `out`, the others use `work`.
+hipError_t batch_solve(mpois_plan_s* pl, const void* const* in, int in_f64, void* const* out, int out_f64,
+                       void* const* work, int work_f64, bool update, hipStream_t s) {
+  BatchState& B = pl->batch;
+  const size_t np = B.passes.size();
+  for (size_t p = 0; p < np; ++p) {
+    BatchPassArgs b{};
+    b.args = static_cast<const PassArgs*>(B.passes[p].args.p);
+    b.src_tab = p == 0 ? in : static_cast<const void* const*>(work);
+    b.src_f64 = p == 0 ? in_f64 : work_f64;
+    const bool last = p + 1 == np;
+    b.dst_tab = last ? out : work;
+    b.dst_f64 = last ? out_f64 : work_f64;
+    b.update = (last && update) ? 1 : 0;
+    b.shift_base = static_cast<const double*>(pl->scalars.p) + S_SHIFT;
+    b.shift_stride = S_COUNT;
+    for (const BatchGroup& g : B.passes[p].groups) {
+      b.tile_prob = static_cast<const int*>(g.tile_prob.p);
+      b.tile_idx = static_cast<const int*>(g.tile_idx.p);
+      hipError_t e = launch_line_pass_batch(g.cfg, b, g.blocks, g.lds, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t batch_resid(mpois_plan_s* pl, const void* const* phi, const void* const* g, void* const* r, bool use_mg,
+                       hipStream_t s) {
+  BatchState& B = pl->batch;
+  BatchResidArgs b{};
+  b.args = static_cast<const ResidArgs*>(B.resid_args.p);
+  b.blk_prob = static_cast<const int*>(B.blk_prob.p);
+  b.blk_start = static_cast<const int*>(B.blk_start.p);
+  b.blk_count = static_cast<const int*>(B.blk_count.p);
+  b.phi_tab = phi;
+  b.g_tab = g;
+  b.r_tab = r;
+  b.r_f64 = 0;
+  b.use_mg = use_mg ? 1 : 0;
+  b.scalars = static_cast<double*>(pl->scalars.p);
+  b.partials = static_cast<double*>(B.partials.p);
+  hipError_t e = launch_resid_batch(b, B.resid_blocks, s);
+  if (e != hipSuccess) return e;
+  return launch_finalize_batch(b.partials, b.blk_start, b.blk_count, static_cast<const double*>(B.inv_wsum.p),
+                               b.scalars, int(pl->subs.size()), s);
+}
+
+hipError_t enqueue_batch(mpois_plan_s* pl, hipStream_t s) {
+  BatchState& B = pl->batch;
+  const size_t count = pl->subs.size();
+  hipError_t e = hipMemcpyAsync(B.rhs_tab.p, B.host_rhs.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(B.phi_tab.p, B.host_phi.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  auto rhs = static_cast<const void* const*>(B.rhs_tab.p);
+  auto phi = static_cast<void* const*>(B.phi_tab.p);
+  if (pl->prec == MPOIS_F64) return batch_solve(pl, rhs, 1, phi, 1, phi, 1, false, s);
+  if (pl->prec == MPOIS_F32) return batch_solve(pl, rhs, 0, phi, 0, phi, 0, false, s);
+  auto work = static_cast<void* const*>(B.work_tab.p);
+  if (B.any_singular && (e = batch_resid(pl, rhs, rhs, nullptr, false, s)) != hipSuccess) return e;
+  if ((e = batch_solve(pl, rhs, 1, phi, 1, work, 0, false, s)) != hipSuccess) return e;
+  for (int it = 0; it < pl->max_iter; ++it) {
+    if ((e = batch_resid(pl, static_cast<const void* const*>(static_cast<const void*>(phi)), rhs, work, true, s)) !=
+        hipSuccess)
+      return e;
+    if ((e = batch_solve(pl, static_cast<const void* const*>(static_cast<const void*>(work)), 0, phi, 1, work, 0,
+                         true, s)) != hipSuccess)
       return e;
   }
   return hipSuccess;
@@ -801,6 +998,11 @@ mpois_status mpois_execute_batch(mpois_plan pl, const void* const* rhs, void* co
   pl->last_rhs_b.assign(rhs, rhs + count);
   pl->last_phi_b.assign(phi, phi + count);
   pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
+  if (pl->batched) {
+    pl->batch.host_rhs.assign(rhs, rhs + count);
+    pl->batch.host_phi.assign(phi, phi + count);
+    return enqueue_batch(pl, s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
+  }
   for (size_t i = 0; i < count; ++i)
     if (enqueue_one(pl, pl->subs[i], i, rhs[i], phi[i], s) != hipSuccess) return MPOIS_ERR_DEVICE;
   return MPOIS_OK;

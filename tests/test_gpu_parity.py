@@ -167,3 +167,64 @@ def test_neumann_cube_512(prec, max_iter):
     err = rel_err(out, ref)
     print(f"[parity] neumann cube 512 {prec}: rel err {err:.3e} resid {info['rel_resid']:.3e}", flush=True)
     assert err <= 1e-12
+
+
+# ------------------------------------------------------------------ batches of independent grids
+def _batch_check(descs, prec, max_iter=2, n_oracle=None):
+    mp = _mp()
+    dt = torch.float32 if prec == "f32" else torch.float64
+    rhs = [torch.as_tensor(workloads.batch_rhs(d, i, seed=11), dtype=dt).cuda() for i, d in enumerate(descs)]
+    phi = [torch.empty_like(r) for r in rhs]
+    plan = mp.BatchPlan(descs, prec=prec, max_iter=max_iter)
+    plan.solve(rhs, phi)
+    torch.cuda.synchronize()
+    worst = 0.0
+    idx = range(len(descs)) if n_oracle is None else range(0, len(descs), max(1, len(descs) // n_oracle))
+    for i in idx:
+        d = descs[i]
+        ref = oracle_solve(rhs[i].double().cpu().numpy(), d["shape"], d["h"], d["bc"], d["grid"], d["approx"])
+        worst = max(worst, rel_err(phi[i].double().cpu().numpy(), ref))
+    info = plan.info()
+    plan.close()
+    return worst, info
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32r"])
+def test_batch_small_mixed(prec):
+    print(f"[parity] batch of 60 small 2D grids, {prec}", flush=True)
+    descs = workloads.batch_2d(count=60, lo=5, hi=90, seed=21)
+    worst, info = _batch_check(descs, prec)
+    assert worst <= TOL[prec], worst
+    if prec != "f32":
+        assert info["rel_resid"] < 1e-10
+
+
+def test_batch_matches_single_plans():
+    descs = workloads.batch_2d(count=12, lo=30, hi=140, seed=22)
+    mp = _mp()
+    rhs = [torch.as_tensor(workloads.batch_rhs(d, i), dtype=torch.float64).cuda() for i, d in enumerate(descs)]
+    phi_b = [torch.empty_like(r) for r in rhs]
+    mp.BatchPlan(descs, prec="f64").solve(rhs, phi_b)
+    for i, d in enumerate(descs):
+        single = mp.Plan.from_desc(d, prec="f64").solve(rhs[i])
+        torch.cuda.synchronize()
+        assert torch.allclose(single, phi_b[i], rtol=0, atol=0), i  # same kernels, same tables: bit-identical
+
+
+def test_batch_full_size_subset():
+    """The 2048-grid workload (sides 64..1024): every grid's residual, and a
+    spread subset against the oracle."""
+    print("[parity] batch 2048 grids, sides 64..1024, f32r", flush=True)
+    descs = workloads.batch_2d(count=2048, seed=4)
+    mp = _mp()
+    rhs = [torch.as_tensor(workloads.batch_rhs(d, i), dtype=torch.float64).cuda() for i, d in enumerate(descs)]
+    phi = [torch.empty_like(r) for r in rhs]
+    plan = mp.BatchPlan(descs, prec="f32r", max_iter=2)
+    plan.solve(rhs, phi)
+    info = plan.info()
+    assert info["rel_resid"] < 1e-11, info
+    for i in range(0, 2048, 128):
+        d = descs[i]
+        ref = oracle_solve(rhs[i].cpu().numpy(), d["shape"], d["h"], d["bc"], d["grid"], "fd")
+        assert rel_err(phi[i].cpu().numpy(), ref) <= 1e-12, (i, d)
+    plan.close()
