@@ -104,11 +104,23 @@ def test_3d_mixed_kinds(prec):
 
 
 def test_3d_several_tiles_and_tails():
-    # lines per tile are 16-32; these shapes leave partial tiles on every axis
+    # lines per tile are 2-32; these shapes leave partial tiles on every axis
     for shape in [(33, 17, 65), (3, 50, 7), (1, 1, 40), (40, 1, 1), (2, 2, 2)]:
         for kinds in ([("P", "v"), ("D", "s"), ("N", "s")], [("N", "v"), ("N", "v"), ("D", "v")]):
+            if any(k == ("N", "v") and n < 2 for k, n in zip(kinds, shape)):
+                continue  # a vertex Neumann axis needs two nodes
             check(shape, kinds, "fd", "f64", seed=6)
             check(shape, kinds, "fd", "f32", seed=6)
+
+
+def test_invalid_plans_are_refused():
+    mp = _mp()
+    with pytest.raises(mp.MpoisError) as e:
+        mp.Plan((40, 1), (0.1, 0.1), ("P", "N"), ("v", "v"))
+    assert e.value.status == 1
+    with pytest.raises(mp.MpoisError) as e:
+        mp.Plan((8, 8), (0.1, 0.1), ("P", "D"), ("v", "v"), approx="ps", prec="f32r")
+    assert e.value.status == 2
 
 
 # ------------------------------------------------------------------ refinement
