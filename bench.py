@@ -1,15 +1,22 @@
 """Benchmark of the fast Poisson solve on one MI355X.
 
-Default workload: 512^3 all-Neumann vertex grid (DCT-I on every axis), second-
-order finite differences, h = 1/511, right-hand side = 64 seeded Gaussian blobs
-(sigma 0.02) minus its mean.  One step = one solve in FP32 with FP64 residual
-refinement (fixed number of corrections) -- the forward transforms, the
-eigenvalue division with the zero mode removed, the inverse transforms, the
-FP64 stencil residual, zero-mode reductions and the FP64 update.  The plain
-FP64 solve of the same input is timed beside it, and the CPU oracle (dense
-FP64 transform matrices) is timed on the host on the same input.
+Default workload (`--workload neumann512`): 512^3 all-Neumann vertex grid
+(DCT-I on every axis), second-order finite differences, h = 1/511, right-hand
+side = 64 seeded Gaussian blobs (sigma 0.02) minus its mean.  One step = one
+solve in FP32 with FP64 residual refinement (fixed number of corrections): the
+forward transforms, the eigenvalue division with the zero mode removed, the
+inverse transforms, the FP64 stencil residual, the zero-mode reductions and
+the FP64 update.  The plain FP64 solve of the same input is timed beside it,
+and the CPU oracle (dense FP64 transform matrices) is timed on the host on the
+same input.
 
-Prints one JSON line (see the keys below).  Progress goes to stderr.
+Other workloads (one JSON line each, same keys):
+  periodic32  32^3 periodic FD, FP64, one solve per step, eager and graph-replayed
+  mixed256    256^3 staggered P/D/N box, FP64 and FP32, FD and pseudo-spectral
+  batch2048   2048 independent 2D grids (sides 64..1024), FP32 + refinement, one batched launch set
+  channel     1024x512x256 channel, graph-captured FP32 + refinement, stream of RHS
+
+Prints one JSON line per workload on stdout; progress goes to stderr.
 """
 
 import argparse
@@ -30,37 +37,89 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_solves(plan, rhs, phi, steps, warmup):
+def timed(fn, steps, warmup):
+    """Average ms per call of fn() over `steps` calls after `warmup`, by HIP events."""
     import torch
     for _ in range(warmup):
-        plan.solve(rhs, phi)
+        fn()
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     start.record()
     for _ in range(steps):
-        plan.solve(rhs, phi)
+        fn()
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return start.elapsed_time(end) / steps, wall / steps * 1e3
 
 
-def kernel_roofline(records):
-    """Dominant kernel (largest total time) of a profiled execute: bytes / duration."""
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("line_pass.h", "cfgs.h"):
+        with open(os.path.join(ROOT, "paper_1409_8116_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter profile, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "line_pass_neumann512_hbm_counters.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    want = kernel_sources_hash()
+    for ln in lines:
+        if ln.startswith("traffic:"):
+            kv = dict(x.split("=", 1) for x in ln[len("traffic:"):].strip().split(" ") if "=" in x)
+            if kv.get("sources") == want and kernel.replace(" ", "") in ln.replace(" ", ""):
+                return float(kv["bytes_per_launch"])
+    return None
+
+
+def kernel_roofline(records, reps):
+    """Dominant kernel (largest total time) of profiled executes: bytes / duration."""
     by = {}
     for r in records:
-        k = r["kernel"]
-        e = by.setdefault(k, {"ms": 0.0, "bytes": 0.0, "count": 0})
+        e = by.setdefault(r["kernel"], {"ms": 0.0, "bytes": 0.0, "count": 0})
         e["ms"] += r["ms"]
         e["bytes"] += r["bytes"]
         e["count"] += 1
     k = max(by, key=lambda x: by[x]["ms"])
     e = by[k]
-    return k, e, by
+    achieved = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+    name = kernel_name(k)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name), "kernel": name,
+            "launches_per_step": e["count"] // reps, "avg_launch_ms": e["ms"] / e["count"],
+            "bytes_per_launch": e["bytes"] / e["count"]}
 
 
-def cpu_baseline(d, g):
+def kernel_name(k):
+    if k == 100:
+        return "resid_kernel"
+    if k == 101:
+        return "finalize_kernel"
+    import paper_1409_8116_amd as mp
+    return mp.kernel_shape_name(k)
+
+
+def profile_plan(make_plan, rhs, reps=3):
+    import torch
+    plan = make_plan()
+    tmp = torch.empty_like(rhs)
+    recs = []
+    for _ in range(reps):
+        plan.solve(rhs, tmp)
+        recs += plan.profile()
+    plan.close()
+    return kernel_roofline(recs, reps)
+
+
+def cpu_oracle(d, g):
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -70,8 +129,194 @@ def cpu_baseline(d, g):
     axes = oracle.axes_from(d["shape"], d["h"], d["bc"], d["grid"])
     t0 = time.perf_counter()
     ref = oracle.solve(g, axes, d["approx"])
-    dt = time.perf_counter() - t0
-    return ref, dt, threads
+    return ref, time.perf_counter() - t0, threads
+
+
+def rel(a, ref):
+    import torch
+    return float(torch.linalg.norm(a.double().cpu() - torch.from_numpy(ref)) / np.linalg.norm(ref))
+
+
+def base_record(args, metric, value, unit, ms, dtype, config):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+# ----------------------------------------------------------------------------- workloads
+def run_neumann(args):
+    import torch
+    import workloads
+    import paper_1409_8116_amd as mp
+    n = args.n
+    log(f"generating {n}^3 Neumann blob input")
+    d, g = workloads.neumann_blobs(n, seed=3)
+    npts = int(np.prod(d["shape"]))
+    rhs = torch.tensor(g, dtype=torch.float64, device="cuda")
+    phi_r = torch.empty_like(rhs)
+    phi_64 = torch.empty_like(rhs)
+    plan_r = mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter)
+    plan_64 = mp.Plan.from_desc(d, prec="f64")
+    log("timing FP32 + refinement")
+    ms_r, wall_r = timed(lambda: plan_r.solve(rhs, phi_r), args.steps, args.warmup)
+    info_r = plan_r.info()
+    log(f"  {ms_r:.3f} ms/solve, rel resid {info_r['rel_resid']:.3e}")
+    log("timing FP64")
+    ms_64, _ = timed(lambda: plan_64.solve(rhs, phi_64), args.steps, args.warmup)
+    info_64 = plan_64.info()
+    log(f"  {ms_64:.3f} ms/solve, rel resid {info_64['rel_resid']:.3e}")
+    roof = profile_plan(lambda: mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, profile=True), rhs)
+    roof64 = profile_plan(lambda: mp.Plan.from_desc(d, prec="f64", profile=True), rhs)
+    log(f"dominant kernel (f32r) {roof['kernel']}: {roof['avg_launch_ms']:.3f} ms avg, {roof['achieved']:.0f} GB/s")
+    log(f"dominant kernel (f64) {roof64['kernel']}: {roof64['avg_launch_ms']:.3f} ms avg, {roof64['achieved']:.0f} GB/s")
+    out = base_record(args, "grid points solved/s (FP32+FP64 refinement to 1e-12 rel. error), with HBM GB/s",
+                      npts / (ms_r * 1e-3), "points/s", ms_r, "f32+f64",
+                      {"workload": f"neumann_vertex_{n}^3_dct1_fd_blobs64", "shape": list(d["shape"]),
+                       "bc": "N,N,N (vertex)", "approx": "fd", "refine_corrections": args.max_iter})
+    out["fp64_path"] = {"points_per_s": npts / (ms_64 * 1e-3), "ms_per_solve": ms_64,
+                        "speed_ratio_f32r_over_f64": ms_64 / ms_r, "roofline": roof64}
+    out["rel_resid"] = {"f32r": info_r["rel_resid"], "f64": info_64["rel_resid"]}
+    out["roofline"] = roof
+    out["wall_ms_per_step"] = wall_r
+    if not args.no_cpu:
+        log("running the CPU oracle on the same input (one full solve)")
+        ref, dt, threads = cpu_oracle(d, g)
+        err_r, err_64 = rel(phi_r, ref), rel(phi_64, ref)
+        log(f"oracle {dt:.1f} s; rel err f32r {err_r:.3e}, f64 {err_64:.3e}")
+        out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+                               "sample": f"one full {n}^3 solve of the same input (dense FP64 transform "
+                                         f"matrices, {dt:.1f} s)"}
+        out["rel_err_vs_oracle"] = {"f32r": err_r, "f64": err_64}
+    return [out]
+
+
+def run_periodic32(args):
+    import torch
+    import workloads
+    import paper_1409_8116_amd as mp
+    d, g = workloads.periodic_noise(32, seed=1)
+    npts = int(np.prod(d["shape"]))
+    rhs = torch.tensor(g, dtype=torch.float64, device="cuda")
+    phi = torch.empty_like(rhs)
+    eager = mp.Plan.from_desc(d, prec="f64")
+    graph = mp.Plan.from_desc(d, prec="f64", graph=True)
+    steps = max(args.steps, 1000)
+    ms_e, _ = timed(lambda: eager.solve(rhs, phi), steps, 50)
+    phi_g = torch.empty_like(rhs)
+    ms_g, _ = timed(lambda: graph.solve(rhs, phi_g), steps, 50)
+    out = base_record(args, "grid points solved/s", npts / (ms_g * 1e-3), "points/s", ms_g, "f64",
+                      {"workload": "periodic_32^3_fd_fp64", "shape": [32, 32, 32]})
+    out["us_per_solve"] = {"eager": ms_e * 1e3, "graph": ms_g * 1e3}
+    out["roofline"] = profile_plan(lambda: mp.Plan.from_desc(d, prec="f64", profile=True), rhs)
+    if not args.no_cpu:
+        ref, dt, threads = cpu_oracle(d, g)
+        out["rel_err_vs_oracle"] = {"eager": rel(phi, ref), "graph": rel(phi_g, ref)}
+        out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+                               "sample": "one 32^3 solve"}
+    return [out]
+
+
+def run_mixed256(args):
+    import torch
+    import workloads
+    import paper_1409_8116_amd as mp
+    outs = []
+    for approx in ("fd", "ps"):
+        d, g, _ = workloads.mixed_modes(256, seed=2, approx=approx)
+        npts = int(np.prod(d["shape"]))
+        ref = None
+        if not args.no_cpu:
+            ref, dt, threads = cpu_oracle(d, g)
+        for prec in ("f64", "f32"):
+            dt_ = torch.float64 if prec == "f64" else torch.float32
+            rhs = torch.tensor(g, dtype=dt_, device="cuda")
+            phi = torch.empty_like(rhs)
+            plan = mp.Plan.from_desc(d, prec=prec)
+            ms, _ = timed(lambda: plan.solve(rhs, phi), args.steps, args.warmup)
+            out = base_record(args, "grid points solved/s", npts / (ms * 1e-3), "points/s", ms, prec,
+                              {"workload": f"mixed_256^3_P-Ds-Ns_{approx}_{prec}", "shape": [256] * 3})
+            out["roofline"] = profile_plan(lambda: mp.Plan.from_desc(d, prec=prec, profile=True), rhs)
+            if ref is not None:
+                out["rel_err_vs_oracle"] = rel(phi, ref)
+                out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+                                       "sample": f"one 256^3 {approx} solve"}
+            outs.append(out)
+    return outs
+
+
+def run_batch(args):
+    import torch
+    import workloads
+    import paper_1409_8116_amd as mp
+    descs = workloads.batch_2d(count=2048, seed=4)
+    npts = sum(int(np.prod(d["shape"])) for d in descs)
+    log(f"batch: 2048 grids, {npts:.3e} points; generating right-hand sides")
+    rhs = [torch.tensor(workloads.batch_rhs(d, i), dtype=torch.float64, device="cuda") for i, d in enumerate(descs)]
+    phi = [torch.empty_like(r) for r in rhs]
+    t0 = time.perf_counter()
+    plan = mp.BatchPlan(descs, prec="f32r", max_iter=args.max_iter)
+    log(f"batch plan built in {time.perf_counter() - t0:.1f} s")
+    ms, _ = timed(lambda: plan.solve(rhs, phi), args.steps, args.warmup)
+    info = plan.info()
+    out = base_record(args, "grid points solved/s", npts / (ms * 1e-3), "points/s", ms, "f32+f64",
+                      {"workload": "batch_2048x2D_64-1024_f32r", "grids": 2048, "points": npts})
+    out["rel_resid_worst"] = info["rel_resid"]
+    if not args.no_cpu:
+        worst, tsum, nsub = 0.0, 0.0, 0
+        for i in range(0, 2048, 64):
+            d = descs[i]
+            ref, dt, threads = cpu_oracle(d, rhs[i].cpu().numpy())
+            worst = max(worst, rel(phi[i], ref))
+            tsum += dt
+            nsub += int(np.prod(d["shape"]))
+        out["rel_err_vs_oracle_subset32"] = worst
+        out["cpu_baseline"] = {"value": nsub / tsum, "unit": "points/s", "cores": threads, "kind": "oracle",
+                               "sample": "32 of the 2048 grids (every 64th)"}
+    return [out]
+
+
+def run_channel(args):
+    import torch
+    import workloads
+    import paper_1409_8116_amd as mp
+    d = workloads.channel_desc()
+    npts = int(np.prod(d["shape"]))
+    nrhs = args.nrhs
+    plan = mp.Plan.from_desc(d, prec="f32r", max_iter=1, graph=True)
+    rhs = torch.empty(d["shape"], dtype=torch.float64, device="cuda")
+    phi = torch.empty_like(rhs)
+    # the graph is captured for this (rhs, phi) pair; each step regenerates rhs in place
+    g0 = workloads.channel_divergence(d, 0, device="cuda")
+    rhs.copy_(g0)
+    plan.solve(rhs, phi)
+    torch.cuda.synchronize()
+    first = phi.clone()
+    total = 0.0
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    worst_resid = 0.0
+    for s in range(nrhs):
+        rhs.copy_(workloads.channel_divergence(d, s, device="cuda"))
+        start.record()
+        plan.solve(rhs, phi)
+        end.record()
+        torch.cuda.synchronize()
+        total += start.elapsed_time(end)
+        if s % 50 == 0 or s == nrhs - 1:
+            worst_resid = max(worst_resid, plan.info()["rel_resid"])
+    ms = total / nrhs
+    out = base_record(args, "grid points solved/s", npts / (ms * 1e-3), "points/s", ms, "f32+f64",
+                      {"workload": f"channel_1024x512x256_P-Ns-P_graph_f32r_{nrhs}rhs", "shape": list(d["shape"])})
+    out["rel_resid_worst_sampled"] = worst_resid
+    if not args.no_cpu:
+        ref, dt, threads = cpu_oracle(d, g0.cpu().numpy())
+        out["rel_err_vs_oracle_rhs0"] = rel(first, ref)
+        out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+                               "sample": "one 1024x512x256 solve (rhs #0)"}
+    return [out]
+
+
+WORKLOADS = {"neumann512": run_neumann, "periodic32": run_periodic32, "mixed256": run_mixed256,
+             "batch2048": run_batch, "channel": run_channel}
 
 
 def main():
@@ -79,93 +324,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="neumann512", choices=sorted(WORKLOADS))
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--max-iter", type=int, default=2)
+    ap.add_argument("--nrhs", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this solver build has no multi-GPU path "
               "(the slab decomposition over RCCL is described, not built)", file=sys.stderr)
         sys.exit(2)
-
     import torch
-    import workloads
-    import paper_1409_8116_amd as mp
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    n = args.n
-    log(f"generating {n}^3 Neumann blob input")
-    d, g = workloads.neumann_blobs(n, seed=3)
-    npts = int(np.prod(d["shape"]))
-    rhs = torch.tensor(g, dtype=torch.float64, device="cuda")
-    phi32r = torch.empty_like(rhs)
-    phi64 = torch.empty_like(rhs)
-
-    plan_r = mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter)
-    plan_64 = mp.Plan.from_desc(d, prec="f64")
-    log("timing FP32 + refinement")
-    ms_r, wall_r = time_solves(plan_r, rhs, phi32r, args.steps, args.warmup)
-    info_r = plan_r.info()
-    log(f"  {ms_r:.3f} ms/solve, rel resid {info_r['rel_resid']:.3e}")
-    log("timing FP64")
-    ms_64, wall_64 = time_solves(plan_64, rhs, phi64, args.steps, args.warmup)
-    info_64 = plan_64.info()
-    log(f"  {ms_64:.3f} ms/solve, rel resid {info_64['rel_resid']:.3e}")
-
-    # live per-kernel timing with HIP events on the launch stream
-    prof_r = mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, profile=True)
-    prof_64 = mp.Plan.from_desc(d, prec="f64", profile=True)
-    tmp = torch.empty_like(rhs)
-    recs_r, recs_64 = [], []
-    for _ in range(3):
-        prof_r.solve(rhs, tmp)
-        recs_r += prof_r.profile()
-        prof_64.solve(rhs, tmp)
-        recs_64 += prof_64.profile()
-    k_r, e_r, by_r = kernel_roofline(recs_r)
-    k_64, e_64, _ = kernel_roofline(recs_64)
-    achieved = e_r["bytes"] / (e_r["ms"] * 1e-3) / 1e9
-    achieved_64 = e_64["bytes"] / (e_64["ms"] * 1e-3) / 1e9
-    log(f"dominant kernel (f32r) cfg {k_r}: {e_r['count'] // 3} launches/solve, "
-        f"{e_r['ms'] / e_r['count']:.3f} ms avg, {achieved:.0f} GB/s")
-    log(f"dominant kernel (f64) cfg {k_64}: {e_64['ms'] / e_64['count']:.3f} ms avg, {achieved_64:.0f} GB/s")
-    del prof_r, prof_64, tmp
-
-    out = {
-        "metric": "grid points solved/s (FP32+FP64 refinement to 1e-12 rel. error), with HBM GB/s",
-        "value": npts / (ms_r * 1e-3),
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_r,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"neumann_vertex_{n}^3_dct1_fd_blobs64", "shape": list(d["shape"]),
-                   "bc": "N,N,N (vertex)", "approx": "fd", "refine_corrections": args.max_iter},
-        "fp64_path": {"points_per_s": npts / (ms_64 * 1e-3), "ms_per_solve": ms_64,
-                      "speed_ratio_f32r_over_f64": ms_64 / ms_r},
-        "rel_resid": {"f32r": info_r["rel_resid"], "f64": info_64["rel_resid"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"line_pass cfg {k_r}", "launches_per_step": e_r["count"] // 3,
-                     "fp64_line_pass_GBs": achieved_64},
-        "wall_ms_per_step": wall_r,
-    }
-    if not args.no_cpu:
-        log("running the CPU oracle on the same input (one full solve)")
-        ref, dt, threads = cpu_baseline(d, g)
-        err_r = float(torch.linalg.norm(phi32r.cpu() - torch.from_numpy(ref)) / np.linalg.norm(ref))
-        err_64 = float(torch.linalg.norm(phi64.cpu() - torch.from_numpy(ref)) / np.linalg.norm(ref))
-        log(f"oracle {dt:.1f} s; rel err f32r {err_r:.3e}, f64 {err_64:.3e}")
-        out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
-                               "sample": f"one full {n}^3 solve of the same input (dense FP64 transform "
-                                         f"matrices, {dt:.1f} s)"}
-        out["rel_err_vs_oracle"] = {"f32r": err_r, "f64": err_64}
-    print(json.dumps(out), flush=True)
+    for rec in WORKLOADS[args.workload](args):
+        print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

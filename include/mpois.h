@@ -152,6 +152,11 @@ mpois_status mpois_axis_eigenvalues(int bc, int grid, int approx, int64_t n, dou
 mpois_status mpois_axis_plan(int bc, int grid, int64_t n, int* kind_fwd, int* kind_bwd, int* M, int* P,
                              int* radices, int cap, int* nradix);
 
+/* Shape of line-transform kernel configuration `cfg` (the kernel ids reported
+ * by mpois_profile): element size in bytes, line pairs per workgroup tile,
+ * threads per workgroup, longest DFT work length.  INVALID if out of range. */
+mpois_status mpois_kernel_shape(int cfg, int* elem_bytes, int* pairs, int* threads, int* max_len);
+
 #ifdef __cplusplus
 }
 #endif

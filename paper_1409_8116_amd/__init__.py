@@ -84,7 +84,8 @@ def load_library():
                                            ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     lib.mpois_axis_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.POINTER(ctypes.c_int)] * 5 + \
         [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-    for name in ("mpois_plan_create", "mpois_plan_create_batch", "mpois_execute", "mpois_execute_batch",
+    lib.mpois_kernel_shape.argtypes = [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
+    for name in ("mpois_kernel_shape", "mpois_plan_create", "mpois_plan_create_batch", "mpois_execute", "mpois_execute_batch",
                  "mpois_get_info", "mpois_destroy", "mpois_validate", "mpois_axis_eigenvalues", "mpois_axis_plan",
                  "mpois_profile"):
         getattr(lib, name).restype = ctypes.c_int
@@ -135,6 +136,16 @@ def axis_plan(bc, grid, n):
         raise MpoisError(st, "axis_plan")
     return {"forward": KIND_NAMES[vals[0].value], "backward": KIND_NAMES[vals[1].value], "M": vals[2].value,
             "P": vals[3].value, "radices": list(rad[:nr.value])}
+
+
+def kernel_shape_name(cfg):
+    """Readable name of a line-transform kernel configuration id."""
+    v = [ctypes.c_int() for _ in range(4)]
+    st = load_library().mpois_kernel_shape(int(cfg), *[ctypes.byref(x) for x in v])
+    if st:
+        return f"line_pass#{cfg}"
+    t = "double" if v[0].value == 8 else "float"
+    return f"line_pass<{t}, {v[1].value}, {v[2].value}, {v[3].value}>"
 
 
 def _stream_ptr(stream):

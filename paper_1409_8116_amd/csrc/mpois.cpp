@@ -1058,6 +1058,17 @@ mpois_status mpois_destroy(mpois_plan pl) {
 
 size_t mpois_workspace_bytes(mpois_plan pl) { return pl ? pl->bytes : 0; }
 
+mpois_status mpois_kernel_shape(int cfg, int* elem_bytes, int* pairs, int* threads, int* max_len) {
+  if (cfg < 0 || cfg >= num_kernel_cfgs()) return MPOIS_ERR_INVALID;
+  int f64, np, nt, pmax;
+  kernel_cfg(cfg, &f64, &np, &nt, &pmax);
+  if (elem_bytes) *elem_bytes = f64 ? 8 : 4;
+  if (pairs) *pairs = np;
+  if (threads) *threads = nt;
+  if (max_len) *max_len = pmax;
+  return MPOIS_OK;
+}
+
 mpois_status mpois_profile(mpois_plan pl, void* stream, int cap, double* ms, double* bytes, int* kernel, int* count) {
   if (!pl || !count || cap < 0) return MPOIS_ERR_INVALID;
   if (!(pl->flags & MPOIS_FLAG_PROFILE)) return MPOIS_ERR_INVALID;
