@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpois.so")
-SOURCES = ["lp_f64.hip", "lp_f32.hip", "aux.hip", "dispatch.cpp", "mpois.cpp", "tune.cpp"]
+SOURCES = ["aux.hip", "dispatch.cpp", "mpois.cpp", "tune.cpp"]
+NUM_SHAPES = 11  # entries of cfgs.h; lp_inst.hip is compiled once per shape
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in device code
@@ -15,20 +16,30 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
-def build(verbose=False, jobs=4):
+def build(verbose=False, jobs=None):
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs, procs = [], []
+    jobs = jobs or max(1, min(16, os.cpu_count() or 1))
+    cmds, objs = [], []
+    for i in range(NUM_SHAPES):
+        obj = os.path.join(objdir, f"lp_inst_{i}.o")
+        cmds.append([HIPCC] + FLAGS + [f"-DMPOIS_CFG={i}", "-c", os.path.join(CSRC, "lp_inst.hip"), "-o", obj])
+        objs.append(obj)
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        cmds.append([HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    running = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append(subprocess.Popen(cmd))
-        objs.append(obj)
-    for p in procs:
+        running.append(subprocess.Popen(cmd))
+        while len([p for p in running if p.poll() is None]) >= jobs:
+            running[0].wait() if running[0].poll() is None else None
+            import time
+            time.sleep(0.2)
+    for p in running:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp"

@@ -6,30 +6,38 @@
 
 namespace mpois {
 
-hipError_t launch_line_pass_f64(int i, const PassArgs& a, hipStream_t s, size_t lds);
-hipError_t launch_line_pass_f32(int i, const PassArgs& a, hipStream_t s, size_t lds);
-hipError_t launch_line_pass_batch_f64(int i, const BatchPassArgs& b, int blocks, hipStream_t s, size_t lds);
-hipError_t launch_line_pass_batch_f32(int i, const BatchPassArgs& b, int blocks, hipStream_t s, size_t lds);
-hipError_t prepare_line_pass_f64();
-hipError_t prepare_line_pass_f32();
+// one set per shape, defined in lp_inst.hip compiled with MPOIS_CFG = shape id
+#define MPOIS_DECL(I)                                                                                      \
+  hipError_t launch_line_pass_cfg##I(const PassArgs& a, hipStream_t s, size_t lds);                        \
+  hipError_t launch_line_pass_batch_cfg##I(const BatchPassArgs& b, int blocks, hipStream_t s, size_t lds); \
+  hipError_t prepare_line_pass_cfg##I();
+MPOIS_DECL(0) MPOIS_DECL(1) MPOIS_DECL(2) MPOIS_DECL(3) MPOIS_DECL(4) MPOIS_DECL(5) MPOIS_DECL(6)
+MPOIS_DECL(7) MPOIS_DECL(8) MPOIS_DECL(9) MPOIS_DECL(10)
+#undef MPOIS_DECL
 
 namespace {
 struct KernelCfg {
-  int f64, np, nt, pmax;
+  int f64, np, nt, pmax, rader;
 };
 const KernelCfg kCfgs[] = {
-#define X(T, NP, NT, PMAX) {sizeof(T) == 8, NP, NT, PMAX},
-    MPOIS_CFGS_F64(X) MPOIS_CFGS_F32(X)
+#define X(ID, T, NP, NT, PMAX, RADER) {sizeof(T) == 8, NP, NT, PMAX, RADER},
+    MPOIS_CFGS(X)
 #undef X
 };
-constexpr int kNumF64 = 0
-#define X(T, NP, NT, PMAX) +1
-    MPOIS_CFGS_F64(X)
-#undef X
-    ;
+constexpr int kNum = sizeof(kCfgs) / sizeof(kCfgs[0]);
+static_assert(kNum == 11, "update the per-shape function tables below");
+
+using LaunchFn = hipError_t (*)(const PassArgs&, hipStream_t, size_t);
+using LaunchBatchFn = hipError_t (*)(const BatchPassArgs&, int, hipStream_t, size_t);
+using PrepareFn = hipError_t (*)();
+#define MPOIS_ROW(F) F##0, F##1, F##2, F##3, F##4, F##5, F##6, F##7, F##8, F##9, F##10
+const LaunchFn kLaunch[kNum] = {MPOIS_ROW(launch_line_pass_cfg)};
+const LaunchBatchFn kLaunchBatch[kNum] = {MPOIS_ROW(launch_line_pass_batch_cfg)};
+const PrepareFn kPrepare[kNum] = {MPOIS_ROW(prepare_line_pass_cfg)};
+#undef MPOIS_ROW
 }  // namespace
 
-int num_kernel_cfgs() { return int(sizeof(kCfgs) / sizeof(kCfgs[0])); }
+int num_kernel_cfgs() { return kNum; }
 
 void kernel_cfg(int i, int* f64, int* np, int* nt, int* pmax) {
   *f64 = kCfgs[i].f64;
@@ -37,6 +45,8 @@ void kernel_cfg(int i, int* f64, int* np, int* nt, int* pmax) {
   *nt = kCfgs[i].nt;
   *pmax = kCfgs[i].pmax;
 }
+
+int kernel_cfg_rader(int i) { return kCfgs[i].rader; }
 
 // LDS bytes: the larger of the real tile (2 NP rows, odd pitch) and the
 // complex work buffer (NP pairs of P values).
@@ -50,21 +60,21 @@ size_t line_pass_lds(int cfg, int n, int P) {
 }
 
 hipError_t prepare_kernels() {
-  hipError_t e = prepare_line_pass_f64();
-  if (e == hipSuccess) e = prepare_line_pass_f32();
-  return e;
+  for (int i = 0; i < kNum; ++i) {
+    hipError_t e = kPrepare[i]();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s) {
-  if (cfg < 0 || cfg >= num_kernel_cfgs()) return hipErrorInvalidValue;
-  const size_t lds = line_pass_lds(cfg, a.ax.n, a.ax.P);
-  return cfg < kNumF64 ? launch_line_pass_f64(cfg, a, s, lds) : launch_line_pass_f32(cfg - kNumF64, a, s, lds);
+  if (cfg < 0 || cfg >= kNum) return hipErrorInvalidValue;
+  return kLaunch[cfg](a, s, line_pass_lds(cfg, a.ax.n, a.ax.P));
 }
 
 hipError_t launch_line_pass_batch(int cfg, const BatchPassArgs& b, int blocks, size_t lds, hipStream_t s) {
-  if (cfg < 0 || cfg >= num_kernel_cfgs()) return hipErrorInvalidValue;
-  return cfg < kNumF64 ? launch_line_pass_batch_f64(cfg, b, blocks, s, lds)
-                       : launch_line_pass_batch_f32(cfg - kNumF64, b, blocks, s, lds);
+  if (cfg < 0 || cfg >= kNum) return hipErrorInvalidValue;
+  return kLaunchBatch[cfg](b, blocks, s, lds);
 }
 
 }  // namespace mpois

@@ -51,6 +51,114 @@ __device__ __forceinline__ int opaque_tid() {
   return t;
 }
 
+// ----------------------------------------------------------------------------- compile-time trig
+// cos / sin of 2 pi k / n evaluated by the compiler: reduce to [0, pi/4] by the
+// quadrant and octant symmetries, then sum the Taylor series (enough terms for
+// double precision on that interval).
+constexpr double kTwoPi = 6.283185307179586476925286766559005768;
+constexpr double ct_sin_series(double x) {
+  double term = x, sum = x;
+  for (int i = 1; i < 14; ++i) {
+    term *= -x * x / double((2 * i) * (2 * i + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_cos_series(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int i = 1; i < 14; ++i) {
+    term *= -x * x / double((2 * i - 1) * (2 * i));
+    sum += term;
+  }
+  return sum;
+}
+// (cos, sin)(2 pi k / n) for integers; 8k/n selects the octant exactly.
+constexpr double ct_cs(long k, long n, bool want_sin) {
+  long r = ((k % n) + n) % n;
+  long oct = (8 * r) / n;             // 0..7
+  // angle within the octant, measured from the octant's start or end
+  double t = kTwoPi * double(8 * r - oct * n) / double(8 * n);  // in [0, pi/4)
+  double c = 0, s = 0;
+  switch (oct) {
+    case 0: c = ct_cos_series(t); s = ct_sin_series(t); break;
+    case 1: { double u = kTwoPi / 8 - t; c = ct_sin_series(u); s = ct_cos_series(u); break; }
+    case 2: c = -ct_sin_series(t); s = ct_cos_series(t); break;
+    case 3: { double u = kTwoPi / 8 - t; c = -ct_cos_series(u); s = ct_sin_series(u); break; }
+    case 4: c = -ct_cos_series(t); s = -ct_sin_series(t); break;
+    case 5: { double u = kTwoPi / 8 - t; c = -ct_sin_series(u); s = -ct_cos_series(u); break; }
+    case 6: c = ct_sin_series(t); s = -ct_cos_series(t); break;
+    default: { double u = kTwoPi / 8 - t; c = ct_cos_series(u); s = -ct_sin_series(u); break; }
+  }
+  return want_sin ? s : c;
+}
+constexpr double ct_cos(long k, long n) { return ct_cs(k, n, false); }
+constexpr double ct_sin(long k, long n) { return ct_cs(k, n, true); }
+
+// Table of (cos, sin)(2 pi k / N), k < N, built by the compiler.
+template <int N>
+struct TwTable {
+  double c[N];
+  double s[N];
+  constexpr TwTable() : c(), s() {
+    for (int k = 0; k < N; ++k) {
+      c[k] = ct_cos(k, N);
+      s[k] = ct_sin(k, N);
+    }
+  }
+};
+template <int N>
+struct Tw {
+  static constexpr TwTable<N> t{};
+};
+
+// Modular arithmetic for the Rader permutation (compile time).
+constexpr long ct_powmod(long b, long e, long m) {
+  long r = 1;
+  b %= m;
+  while (e > 0) {
+    if (e & 1) r = r * b % m;
+    b = b * b % m;
+    e >>= 1;
+  }
+  return r;
+}
+// Smallest primitive root of a prime p (declared below the tables that use it).
+constexpr long ct_primroot(long p);
+
+// Rader index tables of a prime R: gq[q] = g^q mod R, gi[m] = g^{-m} mod R.
+template <int R>
+struct RaderTable {
+  int gq[R - 1];
+  int gi[R - 1];
+  constexpr RaderTable() : gq(), gi() {
+    const long g = ct_primroot(R);
+    const long ginv = ct_powmod(g, R - 2, R);
+    for (int q = 0; q < R - 1; ++q) {
+      gq[q] = int(ct_powmod(g, q, R));
+      gi[q] = int(ct_powmod(ginv, q, R));
+    }
+  }
+};
+template <int R>
+struct Rader {
+  static constexpr RaderTable<R> t{};
+};
+
+constexpr long ct_primroot(long p) {
+  for (long g = 2; g < p; ++g) {
+    bool ok = true;
+    for (long q = 2; q <= p - 1 && ok; ++q) {
+      bool prime = true;
+      for (long d = 2; d * d <= q; ++d)
+        if (q % d == 0) prime = false;
+      if (prime && (p - 1) % q == 0 && ct_powmod(g, (p - 1) / q, p) == 1) ok = false;
+    }
+    if (ok) return g;
+  }
+  return 0;
+}
+
+
 // ----------------------------------------------------------------------------- codelets
 // Forward DFT (kernel e^{-2 pi i jk/R}) of R values held in registers.
 
@@ -103,9 +211,9 @@ __device__ __forceinline__ void dft3(cx<T>* v) {
 
 // Odd radix R >= 5 from the symmetric form: with s_j = v_j + v_{R-j} and
 // d_j = v_j - v_{R-j},  X_k = v_0 + sum_j s_j cos(2 pi jk/R) - i sum_j d_j sin(2 pi jk/R)
-// and X_{R-k} is the same with +i.  cs[j] = (cos, sin)(2 pi j/R).
+// and X_{R-k} is the same with +i.
 template <typename T, int R>
-__device__ __forceinline__ void dft_odd(cx<T>* v, const cx<T>* __restrict__ cs) {
+__device__ __forceinline__ void dft_odd(cx<T>* v) {
   constexpr int H = (R - 1) / 2;
   cx<T> s[H], d[H];
 #pragma unroll
@@ -122,11 +230,12 @@ __device__ __forceinline__ void dft_odd(cx<T>* v, const cx<T>* __restrict__ cs) 
     cx<T> A = a0, B = {T(0), T(0)};
 #pragma unroll
     for (int j = 1; j <= H; ++j) {
-      const cx<T> w = cs[(j * k) % R];
-      A.re += s[j - 1].re * w.re;
-      A.im += s[j - 1].im * w.re;
-      B.re += d[j - 1].re * w.im;
-      B.im += d[j - 1].im * w.im;
+      const T c = T(Tw<R>::t.c[(j * k) % R]);
+      const T sn = T(Tw<R>::t.s[(j * k) % R]);
+      A.re += s[j - 1].re * c;
+      A.im += s[j - 1].im * c;
+      B.re += d[j - 1].re * sn;
+      B.im += d[j - 1].im * sn;
     }
     v[k] = {A.re + B.im, A.im - B.re};
     v[R - k] = {A.re - B.im, A.im + B.re};
@@ -135,12 +244,50 @@ __device__ __forceinline__ void dft_odd(cx<T>* v, const cx<T>* __restrict__ cs) 
 }
 
 template <typename T, int R>
-__device__ __forceinline__ void dft_any(cx<T>* v, const cx<T>* __restrict__ cs) {
-  if constexpr (R == 2) dft2(v);
+__device__ __forceinline__ void dft_any(cx<T>* v);
+
+// Two-level codelet for R = R1 * R2: DFT-R1 over each stride-R2 subsequence,
+// twiddle e^{-2 pi i j2 k1 / R}, DFT-R2 across subsequences, output k1 + R1 k2.
+template <typename T, int R1, int R2>
+__device__ __forceinline__ void dft_2level(cx<T>* v) {
+  constexpr int R = R1 * R2;
+  cx<T> t[R2][R1];
+#pragma unroll
+  for (int j2 = 0; j2 < R2; ++j2) {
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) t[j2][j1] = v[j1 * R2 + j2];
+    dft_any<T, R1>(t[j2]);
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) {
+      if (j2 == 0) continue;
+      const cx<T> w = {T(Tw<R>::t.c[j2 * k1]), T(-Tw<R>::t.s[j2 * k1])};
+      t[j2][k1] = cmul(t[j2][k1], w);
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cx<T> u[R2];
+#pragma unroll
+    for (int j2 = 0; j2 < R2; ++j2) u[j2] = t[j2][k1];
+    dft_any<T, R2>(u);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = u[k2];
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_any(cx<T>* v) {
+  if constexpr (R == 1) return;
+  else if constexpr (R == 2) dft2(v);
   else if constexpr (R == 3) dft3(v);
   else if constexpr (R == 4) dft4(v);
   else if constexpr (R == 8) dft8(v);
-  else dft_odd<T, R>(v, cs);
+  else if constexpr (R == 9) dft_2level<T, 3, 3>(v);
+  else if constexpr (R == 16) dft_2level<T, 4, 4>(v);
+  else if constexpr (R == 32) dft_2level<T, 8, 4>(v);
+  else if constexpr (R == 64) dft_2level<T, 8, 8>(v);
+  else if constexpr (R == 72) dft_2level<T, 8, 9>(v);
+  else dft_odd<T, R>(v);
 }
 
 // ----------------------------------------------------------------------------- Stockham stage
@@ -148,8 +295,7 @@ __device__ __forceinline__ void dft_any(cx<T>* v, const cx<T>* __restrict__ cs) 
 // of the stage are read into registers before the barrier and written after
 // it, so the stage runs in place in one buffer.
 template <typename T, int R, int NP, int NT, int PMAX>
-__device__ __forceinline__ void stage(cx<T>* Z, int P, int ns, const cx<T>* __restrict__ tw,
-                                      const cx<T>* __restrict__ cs) {
+__device__ __forceinline__ void stage(cx<T>* Z, int P, int ns, const cx<T>* __restrict__ tw) {
   constexpr int NB = ((PMAX / R) * NP + NT - 1) / NT;
   const int nbp = P / R;      // butterflies per pair
   const int items = nbp * NP;
@@ -169,7 +315,7 @@ __device__ __forceinline__ void stage(cx<T>* Z, int P, int ns, const cx<T>* __re
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r - 1]);
       }
-      dft_any<T, R>(v[i], cs);
+      dft_any<T, R>(v[i]);
     }
   }
   __syncthreads();
@@ -189,23 +335,92 @@ __device__ __forceinline__ void stage(cx<T>* Z, int P, int ns, const cx<T>* __re
   __syncthreads();
 }
 
+// Prime radix R by Rader's algorithm: with a primitive root g of R, the
+// non-zero outputs are X[g^{-m}] = v_0 + (a (*) d)_m, a cyclic convolution of
+// length R-1 of a_q = v[g^q] with d_j = e^{-2 pi i g^{-j} / R}.  It runs in
+// registers as DFT, pointwise product with dhat = DFT(d) / (R-1), and an
+// inverse DFT (conjugate, DFT, conjugate).  X[0] is the plain sum.
+template <typename T, int R, int NP, int NT, int PMAX>
+__device__ __forceinline__ void stage_rader(cx<T>* Z, int P, int ns, const cx<T>* __restrict__ tw,
+                                            const cx<T>* __restrict__ dhat) {
+  constexpr int L = R - 1;
+  constexpr int NB = ((PMAX / R) * NP + NT - 1) / NT;
+  const int nbp = P / R;
+  const int items = nbp * NP;
+  const int tid = opaque_tid();
+  cx<T> out[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int item = tid + i * NT;
+    if (item < items) {
+      const int p = item % NP;
+      const int b = item / NP;
+      cx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = Z[(b + r * nbp) * NP + p];
+      if (ns > 1) {
+        const int k = b % ns;
+        const cx<T>* w = tw + k * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r - 1]);
+      }
+      cx<T> sum = v[0];
+#pragma unroll
+      for (int r = 1; r < R; ++r) sum = sum + v[r];
+      cx<T> a[L];
+#pragma unroll
+      for (int q = 0; q < L; ++q) a[q] = v[Rader<R>::t.gq[q]];
+      dft_any<T, L>(a);
+#pragma unroll
+      for (int q = 0; q < L; ++q) a[q] = conj(cmul(a[q], dhat[q]));
+      dft_any<T, L>(a);
+      out[i][0] = sum;
+#pragma unroll
+      for (int m = 0; m < L; ++m) out[i][Rader<R>::t.gi[m]] = v[0] + conj(a[m]);
+    }
+  }
+  __syncthreads();
+  const int tid2 = opaque_tid();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int item = tid2 + i * NT;
+    if (item < items) {
+      const int p = item % NP;
+      const int b = item / NP;
+      const int k = b % ns;
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) Z[(base + r * ns) * NP + p] = out[i][r];
+    }
+  }
+  __syncthreads();
+}
+
 // Forward DFT of length P of every pair column of Z.
-template <typename T, int NP, int NT, int PMAX>
+template <typename T, int NP, int NT, int PMAX, int RADER>
 __device__ __forceinline__ void dft_engine(cx<T>* Z, int P, int nstages, const Stage* __restrict__ stp,
-                                        const cx<T>* __restrict__ tw, const cx<T>* __restrict__ cs) {
+                                           const cx<T>* __restrict__ tw, const cx<T>* __restrict__ cs) {
   for (int s = 0; s < nstages; ++s) {
     const Stage st = stp[s];
     const cx<T>* t = tw + st.tw_off;
-    const cx<T>* c = cs + st.cs_off;
     switch (st.radix) {
-      case 2: stage<T, 2, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
-      case 3: stage<T, 3, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
-      case 4: stage<T, 4, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
-      case 5: stage<T, 5, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
-      case 7: stage<T, 7, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
-      case 8: stage<T, 8, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
-      case 11: stage<T, 11, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
-      case 13: stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t, c); break;
+      case 2: stage<T, 2, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 3: stage<T, 3, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 4: stage<T, 4, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 5: stage<T, 5, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 7: stage<T, 7, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 8: stage<T, 8, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 9: stage<T, 9, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 11: stage<T, 11, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 13: stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 16: stage<T, 16, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 32: stage<T, 32, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 64:
+        if constexpr (sizeof(T) == 4) stage<T, 64, NP, NT, PMAX>(Z, P, st.ns, t);
+        break;
+      case 73:
+        if constexpr (RADER != 0) stage_rader<T, 73, NP, NT, PMAX>(Z, P, st.ns, t, cs + st.cs_off);
+        break;
       default: break;  // the planner only emits the radices above
     }
   }
@@ -465,7 +680,18 @@ __device__ __forceinline__ void unpack(cx<T>* Z, T* X, const TileGeom& g, int ki
   }
 }
 
-template <typename T, int NP, int NT, int PMAX>
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8).  Give each XCD a contiguous range of tiles, so that neighbouring
+// tiles -- which share cache lines on the strided axes -- meet in the same L2.
+// A bijection of [0, G) for any G.
+__device__ __forceinline__ int64_t xcd_tile(unsigned b, unsigned G) {
+  constexpr unsigned kXcd = 8;
+  const unsigned q = G / kXcd, r = G % kXcd;
+  const unsigned x = b % kXcd, i = b / kXcd;
+  return int64_t(x) * q + (x < r ? x : r) + i;
+}
+
+template <typename T, int NP, int NT, int PMAX, int RADER>
 __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, unsigned char* smem) {
   constexpr int TL = 2 * NP;
   T* X = reinterpret_cast<T*>(smem);
@@ -516,7 +742,7 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
         for (int item = threadIdx.x; item < items; item += NT) Z[item] = conj(cmul(Z[item], bh[item / NP]));
         __syncthreads();
       }
-      dft_engine<T, NP, NT, PMAX>(Z, ax.P, ax.nstages, ax.st, tw, cs);
+      dft_engine<T, NP, NT, PMAX, RADER>(Z, ax.P, ax.nstages, ax.st, tw, cs);
     }
     unpack<T, NP, NT, PMAX>(Z, X, g, kind, ax, a, l0, phase == 0 && nphase == 2);
   }
@@ -561,16 +787,16 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
 
 
 // One grid: block b owns tile b.
-template <typename T, int NP, int NT, int PMAX>
+template <typename T, int NP, int NT, int PMAX, int RADER>
 __global__ void __launch_bounds__(NT) line_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  line_pass_body<T, NP, NT, PMAX>(a, int64_t(blockIdx.x), smem);
+  line_pass_body<T, NP, NT, PMAX, RADER>(a, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
 // Many grids in one launch: block b works on tile tile_idx[b] of grid
 // tile_prob[b]; the per-grid pass description comes from a device table and
 // the array pointers from per-grid pointer tables.
-template <typename T, int NP, int NT, int PMAX>
+template <typename T, int NP, int NT, int PMAX, int RADER>
 __global__ void __launch_bounds__(NT) line_pass_batch(BatchPassArgs b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int pi = b.tile_prob[blockIdx.x];
@@ -581,29 +807,29 @@ __global__ void __launch_bounds__(NT) line_pass_batch(BatchPassArgs b) {
   a.dst_f64 = b.dst_f64;
   a.update = b.update;
   a.shift = (b.update && b.shift_base && a.singular) ? b.shift_base + int64_t(pi) * b.shift_stride : nullptr;
-  line_pass_body<T, NP, NT, PMAX>(a, int64_t(b.tile_idx[blockIdx.x]), smem);
+  line_pass_body<T, NP, NT, PMAX, RADER>(a, int64_t(b.tile_idx[blockIdx.x]), smem);
 }
 
-template <typename T, int NP, int NT, int PMAX>
+template <typename T, int NP, int NT, int PMAX, int RADER>
 hipError_t launch_lp(const PassArgs& a, hipStream_t s, size_t lds) {
   constexpr int64_t TL = 2 * NP;
   const int64_t blocks = (a.nlines + TL - 1) / TL;
-  hipLaunchKernelGGL((line_pass<T, NP, NT, PMAX>), dim3(unsigned(blocks)), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((line_pass<T, NP, NT, PMAX, RADER>), dim3(unsigned(blocks)), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int NP, int NT, int PMAX>
+template <typename T, int NP, int NT, int PMAX, int RADER>
 hipError_t launch_lp_batch(const BatchPassArgs& b, int blocks, hipStream_t s, size_t lds) {
-  hipLaunchKernelGGL((line_pass_batch<T, NP, NT, PMAX>), dim3(unsigned(blocks)), dim3(NT), lds, s, b);
+  hipLaunchKernelGGL((line_pass_batch<T, NP, NT, PMAX, RADER>), dim3(unsigned(blocks)), dim3(NT), lds, s, b);
   return hipGetLastError();
 }
 
-template <typename T, int NP, int NT, int PMAX>
+template <typename T, int NP, int NT, int PMAX, int RADER>
 hipError_t prepare_lp() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass<T, NP, NT, PMAX>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass<T, NP, NT, PMAX, RADER>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass_batch<T, NP, NT, PMAX>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass_batch<T, NP, NT, PMAX, RADER>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 

@@ -23,6 +23,7 @@
 namespace mpois {
 int num_kernel_cfgs();
 void kernel_cfg(int i, int* f64, int* np, int* nt, int* pmax);
+int kernel_cfg_rader(int i);
 size_t line_pass_lds(int cfg, int n, int P);
 hipError_t prepare_kernels();
 hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s);
@@ -115,17 +116,40 @@ void axis_eigs(int bc, int grid, int approx, int64_t n, double h, double* out) {
   }
 }
 
-// Factor M over the codelet radices; returns false if a larger prime remains.
-bool factor_radices(int64_t M, std::vector<int>* out) {
+// Stockham stages for a DFT of length M: a Rader stage for the prime 73 first
+// (only for work lengths up to 1024, where its kernels are instantiated), then
+// the odd codelet radices, then the power-of-two part split into as few,
+// as even radices as the register budget allows (at most 32 in FP64, 64 in
+// FP32).  Returns false if a prime the codelets do not cover remains.
+constexpr int kRaderPrime = 73;
+bool factor_radices(int64_t M, bool f64, bool allow_rader, std::vector<int>* out) {
   out->clear();
   int64_t m = M;
-  for (int r : kRadices) {
+  if (allow_rader && M <= 1024 && m % kRaderPrime == 0) {
+    out->push_back(kRaderPrime);
+    m /= kRaderPrime;
+  }
+  for (int r : {9, 3, 5, 7, 11, 13}) {
     while (m % r == 0) {
       out->push_back(r);
       m /= r;
     }
   }
-  return m == 1;
+  int e = 0;
+  while (m % 2 == 0) {
+    m /= 2;
+    ++e;
+  }
+  if (m != 1) return false;
+  const int emax = f64 ? 5 : 6;
+  if (e > 0) {
+    const int nst = (e + emax - 1) / emax;
+    for (int i = 0; i < nst; ++i) {
+      const int ei = e / nst + (i < e % nst ? 1 : 0);
+      out->push_back(1 << ei);
+    }
+  }
+  return true;
 }
 
 // Recursive mixed-radix DFT (sign -1) in FP64 for the Bluestein kernel
@@ -163,20 +187,26 @@ struct AxisShape {
   std::vector<int> radices;
 };
 
-AxisShape plan_axis_shape(int bc, int grid, int64_t n) {
+AxisShape plan_axis_shape(int bc, int grid, int64_t n, bool f64) {
   AxisShape s;
   axis_kinds(bc, grid, &s.kind_f, &s.kind_b);
   s.M = axis_dft_length(s.kind_f, n);
-  if (factor_radices(s.M, &s.radices)) {
+  if (factor_radices(s.M, f64, true, &s.radices)) {
     s.P = s.M;
   } else {
     // Bluestein: any cyclic-convolution length >= 2M - 1 works; take the
     // smallest one the codelet radices factor.
     s.bluestein = true;
     s.P = 2 * s.M - 1;
-    while (!factor_radices(s.P, &s.radices)) ++s.P;
+    while (!factor_radices(s.P, f64, false, &s.radices)) ++s.P;
   }
   return s;
+}
+
+bool has_rader(const AxisShape& s) {
+  for (int r : s.radices)
+    if (r == kRaderPrime) return true;
+  return false;
 }
 
 // ---------------------------------------------------------------------------- device tables
@@ -351,8 +381,29 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
         tw.emplace_back(cospi_frac(num, den), -sinpi_frac(num, den));
       }
     st.cs_off = int(cs.size());
-    if (R >= 5 && (R & 1)) {
-      for (int j = 0; j < R; ++j) cs.emplace_back(cospi_frac(2 * j, R), sinpi_frac(2 * j, R));
+    if (R == kRaderPrime) {
+      // Rader kernel spectrum: dhat = DFT_{R-1}(d) / (R-1), d_j = e^{-2 pi i g^{-j} / R}
+      const int L = R - 1;
+      int g = 2;
+      for (; g < R; ++g) {  // smallest primitive root
+        int64_t x = 1;
+        int order = 0;
+        do {
+          x = x * g % R;
+          ++order;
+        } while (x != 1);
+        if (order == L) break;
+      }
+      int64_t ginv = 1;
+      for (int e = 0; e < R - 2; ++e) ginv = ginv * g % R;
+      std::vector<std::complex<double>> d(static_cast<size_t>(L));
+      int64_t gp = 1;
+      for (int j = 0; j < L; ++j) {
+        d[j] = {cospi_frac(2 * gp, R), -sinpi_frac(2 * gp, R)};
+        gp = gp * ginv % R;
+      }
+      host_dft(d);
+      for (auto& x : d) cs.push_back(x / double(L));
     }
     ns *= R;
   }
@@ -397,17 +448,23 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
   return MPOIS_OK;
 }
 
-// Largest-tile kernel configuration of the working precision that holds the line.
-int default_cfg(bool f64, int n, int P) {
-  int best = -1, best_np = 0;
+// Kernel configuration for a line pass: the widest tile (most line pairs) of
+// the working precision that holds the work length in LDS.  The Rader stage is
+// compiled only into some shapes (work length <= 1024; in FP64 the 256-thread
+// ones, where one wave per SIMD leaves the whole register file for its ~300
+// live registers per thread).
+int default_cfg(bool f64, int n, int P, bool rader) {
+  int best = -1, best_np = 0, best_nt = 0;
   for (int i = 0; i < num_kernel_cfgs(); ++i) {
     int cf64, np, nt, pmax;
     kernel_cfg(i, &cf64, &np, &nt, &pmax);
     if ((cf64 != 0) != f64 || P > pmax) continue;
+    if (rader && !kernel_cfg_rader(i)) continue;
     if (line_pass_lds(i, n, P) > size_t(kMaxLds)) continue;
-    if (np > best_np) {
+    if (np > best_np || (np == best_np && nt > best_nt)) {
       best = i;
       best_np = np;
+      best_nt = nt;
     }
   }
   return best;
@@ -444,8 +501,8 @@ mpois_status validate_one(const mpois_grid_desc* g, int approx, int prec, int ma
   }
   // every axis must fit one of the kernel shapes
   for (int d = 0; d < g->ndim; ++d) {
-    AxisShape s = plan_axis_shape(g->bc[d][0], g->grid[d], g->n[d]);
-    if (default_cfg(prec == MPOIS_F64, int(g->n[d]), int(s.P)) < 0) return MPOIS_ERR_UNSUPPORTED;
+    AxisShape s = plan_axis_shape(g->bc[d][0], g->grid[d], g->n[d], prec == MPOIS_F64);
+    if (default_cfg(prec == MPOIS_F64, int(g->n[d]), int(s.P), has_rader(s)) < 0) return MPOIS_ERR_UNSUPPORTED;
   }
   return MPOIS_OK;
 }
@@ -478,7 +535,7 @@ int table_for(mpois_plan_s* pl, int bc, int grid, int64_t n, mpois_status* st) {
   auto it = pl->table_index.find(key);
   if (it != pl->table_index.end()) return it->second;
   AxisTables at;
-  at.shape = plan_axis_shape(bc, grid, n);
+  at.shape = plan_axis_shape(bc, grid, n, pl->f64work);
   at.n = n;
   pl->tables.push_back(at);
   const int idx = int(pl->tables.size()) - 1;
@@ -548,7 +605,7 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
       }
     }
     p.axis = d;
-    p.cfg = default_cfg(pl->f64work, int(g->n[d]), int(at.shape.P));
+    p.cfg = default_cfg(pl->f64work, int(g->n[d]), int(at.shape.P), has_rader(at.shape));
     if (tune_enabled(pl->flags)) p.cfg = tuned_cfg(p.cfg, pl->f64work, int(g->n[d]), int(at.shape.P), inner == 1);
     return p;
   };
@@ -908,7 +965,7 @@ mpois_status mpois_axis_plan(int bc, int grid, int64_t n, int* kind_fwd, int* ki
                              int cap, int* nradix) {
   if (n < 1 || bc < 0 || bc > 2 || (grid != 0 && grid != 1)) return MPOIS_ERR_INVALID;
   if (bc == MPOIS_NEUMANN && grid == MPOIS_VERTEX && n < 2) return MPOIS_ERR_INVALID;
-  AxisShape s = plan_axis_shape(bc, bc == MPOIS_PERIODIC ? MPOIS_VERTEX : grid, n);
+  AxisShape s = plan_axis_shape(bc, bc == MPOIS_PERIODIC ? MPOIS_VERTEX : grid, n, true);
   if (kind_fwd) *kind_fwd = s.kind_f;
   if (kind_bwd) *kind_bwd = s.kind_b;
   if (M) *M = int(s.M);
