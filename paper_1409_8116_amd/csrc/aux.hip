@@ -46,34 +46,76 @@ __device__ __forceinline__ double second_diff(const double* __restrict__ phi, in
 
 constexpr int RESID_NT = 256;
 
-// Block `blk` of `nblk` blocks over one grid: rows are (i0, i1) pairs, threads
-// run along the contiguous axis.  Writes the 4 block partial sums to part[0..3].
+// Second difference along axis 0 from values held in registers.
+__device__ __forceinline__ double second_diff_reg(double lo_v, double c, double hi_v, int64_t i, int64_t n, int clo,
+                                                  double lo_far, double hi_far) {
+  if (clo == C_NONE) return 0.0;
+  double lo, hi;
+  if (i > 0) lo = lo_v;
+  else {
+    switch (clo) {
+      case C_PER: lo = lo_far; break;   // phi[n-1]
+      case C_DV: lo = 0.0; break;
+      case C_DS: lo = -c; break;
+      case C_NV: lo = hi_v; break;      // phi[1]
+      default: lo = c; break;
+    }
+  }
+  if (i < n - 1) hi = hi_v;
+  else {
+    switch (clo) {
+      case C_PER: hi = hi_far; break;   // phi[0]
+      case C_DV: hi = 0.0; break;
+      case C_DS: hi = -c; break;
+      case C_NV: hi = lo_v; break;      // phi[n-2]
+      default: hi = c; break;
+    }
+  }
+  return lo - 2.0 * c + hi;
+}
+
+// Block `blk` of `nblk` over one grid.  The work unit is a strip of RESID_NT
+// consecutive points along axis 2 at a fixed axis-1 index; the block marches
+// the strip along axis 0 keeping the axis-0 neighbours in registers, so each
+// value of phi comes from memory about once.  Writes the 4 block partial sums
+// to part[0..3].
 __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int64_t nblk, double* part) {
   const int64_t n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-  const int64_t rows = n0 * n1;
+  const int64_t strips = (n2 + RESID_NT - 1) / RESID_NT;
+  const int64_t units = strips * n1;
+  const int64_t plane = n1 * n2;
   const double mg = a.mg ? a.mg[0] : 0.0;
   double s_wphi = 0.0, s_wg = 0.0, s_r2 = 0.0, s_g2 = 0.0;
-  for (int64_t row = blk; row < rows; row += nblk) {
-    const int64_t i0 = row / n1, i1 = row - i0 * n1;
-    const double w01 = axis_weight(a.clo[0], i0, n0) * axis_weight(a.clo[1], i1, n1);
-    for (int64_t i2 = threadIdx.x; i2 < n2; i2 += RESID_NT) {
-      const int64_t idx = row * n2 + i2;
-      const double c = a.phi[idx];
+  for (int64_t u = blk; u < units; u += nblk) {
+    const int64_t i1 = u / strips;
+    const int64_t i2 = (u - i1 * strips) * RESID_NT + threadIdx.x;
+    if (i2 >= n2) continue;
+    const int64_t base = i1 * n2 + i2;
+    const double w12 = axis_weight(a.clo[1], i1, n1) * axis_weight(a.clo[2], i2, n2);
+    const double first = a.phi[base];
+    const double last = a.phi[base + (n0 - 1) * plane];
+    double prev = 0.0, cur = first;
+    double next = n0 > 1 ? a.phi[base + plane] : first;
+    for (int64_t i0 = 0; i0 < n0; ++i0) {
+      const int64_t idx = i0 * plane + base;
       const double gv = a.g[idx];
-      const double lap = a.inv_h2[2] * second_diff(a.phi, idx, i2, n2, 1, a.clo[2], c) +
-                         a.inv_h2[1] * second_diff(a.phi, idx, i1, n1, n2, a.clo[1], c) +
-                         a.inv_h2[0] * second_diff(a.phi, idx, i0, n0, n1 * n2, a.clo[0], c);
+      const double lap = a.inv_h2[2] * second_diff(a.phi, idx, i2, n2, 1, a.clo[2], cur) +
+                         a.inv_h2[1] * second_diff(a.phi, idx, i1, n1, n2, a.clo[1], cur) +
+                         a.inv_h2[0] * second_diff_reg(prev, cur, next, i0, n0, a.clo[0], last, first);
       const double gc = gv - mg;
       const double r = gc - lap;
       if (a.r) {
         if (a.r_f64) static_cast<double*>(a.r)[idx] = r;
         else static_cast<float*>(a.r)[idx] = float(r);
       }
-      const double w = w01 * axis_weight(a.clo[2], i2, n2);
-      s_wphi += w * c;
+      const double w = w12 * axis_weight(a.clo[0], i0, n0);
+      s_wphi += w * cur;
       s_wg += w * gv;
       s_r2 += r * r;
       s_g2 += gc * gc;
+      prev = cur;
+      cur = next;
+      next = (i0 + 2 < n0) ? a.phi[idx + 2 * plane] : cur;
     }
   }
   __shared__ double red[4][RESID_NT];
@@ -153,9 +195,10 @@ __global__ void zero_kernel(double* p, int64_t count) {
 }
 
 
+// Blocks of one residual launch: one per (axis-1 index, strip of axis 2), at most 4096.
 int resid_blocks(const int64_t n[3]) {
-  const int64_t rows = n[0] * n[1];
-  return int(rows < 4096 ? rows : 4096);
+  const int64_t units = n[1] * ((n[2] + RESID_NT - 1) / RESID_NT);
+  return int(units < 4096 ? units : 4096);
 }
 
 hipError_t launch_resid(const ResidArgs& a, hipStream_t s) {

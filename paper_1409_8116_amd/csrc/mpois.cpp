@@ -606,7 +606,8 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
     }
     p.axis = d;
     p.cfg = default_cfg(pl->f64work, int(g->n[d]), int(at.shape.P), has_rader(at.shape));
-    if (tune_enabled(pl->flags)) p.cfg = tuned_cfg(p.cfg, pl->f64work, int(g->n[d]), int(at.shape.P), inner == 1);
+    if (tune_enabled(pl->flags) && p.cfg >= 0)
+      p.cfg = tune_pass(a, p.cfg, pl->f64work, has_rader(at.shape), size_t(kMaxLds));
     return p;
   };
   for (int d = D - 1; d >= 1; --d) sp->passes.push_back(axis_pass(d, false, false));
@@ -825,9 +826,9 @@ mpois_status build_batch(mpois_plan_s* pl) {
     rargs[i] = sp.resid;
     rargs[i].singular = sp.singular ? 1 : 0;
     B.any_singular = B.any_singular || sp.singular;
-    const int64_t rows = sp.n[0] * sp.n[1];
+    const int64_t units = sp.n[1] * ((sp.n[2] + 255) / 256);  // residual work units (strips)
     int64_t nb = (sp.npts + 8191) / 8192;
-    nb = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(nb, 256), rows));
+    nb = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(nb, 256), units));
     blk_start[i] = int(blk_prob.size());
     blk_count[i] = int(nb);
     for (int64_t b = 0; b < nb; ++b) blk_prob.push_back(i);

@@ -1,9 +1,13 @@
-// Kernel-shape autotuner interface (tile width / work length per line pass).
+// Kernel-shape autotuner interface.
 #pragma once
+#include <cstddef>
+
+#include "internal.h"
 
 namespace mpois {
 bool tune_enabled(unsigned flags);
-// Best kernel configuration for a line pass of length-n lines whose DFT work
-// length is P; `fallback` is returned when nothing better is known.
-int tuned_cfg(int fallback, bool f64, int n, int P, bool contiguous);
+// Fastest kernel shape for one line pass (measured on scratch arrays of the
+// pass's size, or taken from the per-process / MPOIS_TUNE_CACHE cache);
+// `fallback` if nothing can be measured.
+int tune_pass(const PassArgs& proto, int fallback, bool f64, bool rader, size_t max_lds);
 }  // namespace mpois
