@@ -240,3 +240,66 @@ def test_batch_full_size_subset():
         ref = oracle_solve(rhs[i].cpu().numpy(), d["shape"], d["h"], d["bc"], d["grid"], "fd")
         assert rel_err(phi[i].cpu().numpy(), ref) <= 1e-12, (i, d)
     plan.close()
+
+
+# ------------------------------------------------------------------ captured graphs, autotuned plans
+def test_graph_replay_matches_eager_and_oracle():
+    """A graph-captured refinement plan replayed several times, with eager work and
+    synchronisation between replays: every replay equals the eager result bit for bit
+    and matches the oracle."""
+    d = workloads.channel_desc(64, 32, 16)
+    mp = _mp()
+    eager = mp.Plan.from_desc(d, prec="f32r", max_iter=1)
+    graph = mp.Plan.from_desc(d, prec="f32r", max_iter=1, graph=True)
+    rhs = torch.empty(d["shape"], dtype=torch.float64, device="cuda")
+    phi_g = torch.empty_like(rhs)
+    for s in range(4):
+        print(f"[parity] graph replay {s}", flush=True)
+        rhs.copy_(workloads.channel_divergence(d, s, device="cuda"))
+        ref_eager = eager.solve(rhs)
+        graph.solve(rhs, phi_g)
+        torch.cuda.synchronize()
+        assert torch.equal(ref_eager, phi_g), s
+        ref = oracle_solve(rhs.cpu().numpy(), d["shape"], d["h"], d["bc"], d["grid"], "fd")
+        assert rel_err(phi_g.cpu().numpy(), ref) <= 1e-10
+        _ = (rhs * 2.0).sum().item()  # unrelated eager work between replays
+
+
+def test_graph_replay_new_buffers_recaptures():
+    d = workloads.channel_desc(32, 16, 8)
+    mp = _mp()
+    graph = mp.Plan.from_desc(d, prec="f64", graph=True)
+    for s in range(3):
+        rhs = workloads.channel_divergence(d, s, device="cuda")
+        out = graph.solve(rhs)  # a new phi every call
+        torch.cuda.synchronize()
+        ref = oracle_solve(rhs.cpu().numpy(), d["shape"], d["h"], d["bc"], d["grid"], "fd")
+        assert rel_err(out.cpu().numpy(), ref) <= 1e-12
+
+
+def test_autotuned_plan_matches_default():
+    for kinds, shape in (([("N", "v")] * 3, (40, 66, 34)), ([("P", "v"), ("D", "s"), ("N", "s")], (64, 48, 80))):
+        bc = tuple(k[0] for k in kinds)
+        grid = tuple(k[1] for k in kinds)
+        h = tuple(1.0 / n for n in shape)
+        g = np.random.default_rng(12).standard_normal(shape)
+        ref = oracle_solve(g, shape, h, bc, grid, "fd")
+        for prec in ("f64", "f32r", "f32"):
+            out, _ = gpu_solve(g, shape, h, bc, grid, "fd", prec, tune=True)
+            assert rel_err(out, ref) <= TOL[prec], (kinds, prec)
+
+
+def test_channel_full_size_first_rhs():
+    """The 1024x512x256 channel with a graph-captured FP32+refinement plan."""
+    print("[parity] channel 1024x512x256", flush=True)
+    d = workloads.channel_desc()
+    mp = _mp()
+    plan = mp.Plan.from_desc(d, prec="f32r", max_iter=1, graph=True)
+    rhs = workloads.channel_divergence(d, 0, device="cuda")
+    phi = torch.empty_like(rhs)
+    plan.solve(rhs, phi)
+    info = plan.info()
+    ref = oracle_solve(rhs.cpu().numpy(), d["shape"], d["h"], d["bc"], d["grid"], "fd")
+    err = rel_err(phi.cpu().numpy(), ref)
+    print(f"[parity] channel rel err {err:.3e} resid {info['rel_resid']:.3e}", flush=True)
+    assert err <= 1e-10
