@@ -704,22 +704,48 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
   g.contiguous = (B == 1);
   g.pitch = n | 1;
 
-  // ---- load
-  if (g.contiguous) {
-    const int64_t lend = (l0 + TL < a.nlines) ? l0 + TL : a.nlines;
-    const int valid = int((lend - l0) * n);
-    const int64_t base = l0 * n;
-    for (int f = threadIdx.x; f < TL * n; f += NT) {
-      const int t = f / n, j = f - t * n;
-      X[t * g.pitch + j] = (f < valid) ? load_elem<T>(a.src, base + f, a.src_f64) : T(0);
+  // ---- load.  Every element of the tile is requested before any is written
+  // to LDS, so the whole tile (tens of KB per workgroup) is in flight at once.
+  constexpr int ELD = (2 * NP * PMAX + NT - 1) / NT;  // bound for n <= PMAX
+  {
+    const int tid = opaque_tid();
+    T ld[ELD];
+    if (g.contiguous) {
+      const int64_t lend = (l0 + TL < a.nlines) ? l0 + TL : a.nlines;
+      const int valid = int((lend - l0) * n);
+      const int64_t base = l0 * n;
+#pragma unroll
+      for (int i = 0; i < ELD; ++i) {
+        const int f = tid + i * NT;
+        ld[i] = (f < valid) ? load_elem<T>(a.src, base + f, a.src_f64) : T(0);
+      }
+      // t = f / n without an integer division: f < 2^18 and n <= 8192 keep the
+      // float quotient at least 1/(2n) away from the next integer.
+      const float inv_n = 1.0f / float(n);
+#pragma unroll
+      for (int i = 0; i < ELD; ++i) {
+        const int f = tid + i * NT;
+        if (f < TL * n) {
+          const int t = int((float(f) + 0.5f) * inv_n);
+          X[t * g.pitch + (f - t * n)] = ld[i];
+        }
+      }
+    } else {
+      const int t = tid % TL;
+      const int64_t l = l0 + t;
+      const bool ok = l < a.nlines;
+      const int64_t base = ok ? (l / B) * (int64_t(n) * B) + (l % B) : 0;
+#pragma unroll
+      for (int i = 0; i < ELD; ++i) {
+        const int j = tid / TL + i * (NT / TL);
+        ld[i] = (ok && j < n) ? load_elem<T>(a.src, base + int64_t(j) * B, a.src_f64) : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < ELD; ++i) {
+        const int j = tid / TL + i * (NT / TL);
+        if (j < n) X[j * TL + t] = ld[i];
+      }
     }
-  } else {
-    const int t = threadIdx.x % TL;
-    const int64_t l = l0 + t;
-    const bool ok = l < a.nlines;
-    const int64_t base = ok ? (l / B) * (int64_t(n) * B) + (l % B) : 0;
-    for (int j = threadIdx.x / TL; j < n; j += NT / TL)
-      X[j * TL + t] = ok ? load_elem<T>(a.src, base + int64_t(j) * B, a.src_f64) : T(0);
   }
   __syncthreads();
 
@@ -747,38 +773,59 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
     unpack<T, NP, NT, PMAX>(Z, X, g, kind, ax, a, l0, phase == 0 && nphase == 2);
   }
 
-  // ---- store
-  if (g.contiguous) {
-    const int64_t lend = (l0 + TL < a.nlines) ? l0 + TL : a.nlines;
-    const int valid = int((lend - l0) * n);
-    const int64_t base = l0 * n;
-    for (int f = threadIdx.x; f < valid; f += NT) {
-      const int t = f / n, j = f - t * n;
-      const T x = X[t * g.pitch + j];
+  // ---- store (in update mode the old values are all requested first)
+  {
+    const int tid = opaque_tid();
+    const double shift = (a.update && a.shift) ? a.shift[0] : 0.0;
+    double* d64 = static_cast<double*>(a.dst);
+    float* d32 = static_cast<float*>(a.dst);
+    if (g.contiguous) {
+      const int64_t lend = (l0 + TL < a.nlines) ? l0 + TL : a.nlines;
+      const int valid = int((lend - l0) * n);
+      const int64_t base = l0 * n;
+      const float inv_n = 1.0f / float(n);
+      double old[ELD];
       if (a.update) {
-        double* d = static_cast<double*>(a.dst);
-        d[base + f] = d[base + f] + double(x) - (a.shift ? a.shift[0] : 0.0);
-      } else if (a.dst_f64) {
-        static_cast<double*>(a.dst)[base + f] = double(x);
-      } else {
-        static_cast<float*>(a.dst)[base + f] = float(x);
+#pragma unroll
+        for (int i = 0; i < ELD; ++i) {
+          const int f = tid + i * NT;
+          old[i] = f < valid ? d64[base + f] : 0.0;
+        }
       }
-    }
-  } else {
-    const int t = threadIdx.x % TL;
-    const int64_t l = l0 + t;
-    if (l < a.nlines) {
-      const int64_t base = (l / B) * (int64_t(n) * B) + (l % B);
-      for (int j = threadIdx.x / TL; j < n; j += NT / TL) {
-        const T x = X[j * TL + t];
-        const int64_t o = base + int64_t(j) * B;
+#pragma unroll
+      for (int i = 0; i < ELD; ++i) {
+        const int f = tid + i * NT;
+        if (f < valid) {
+          const int t = int((float(f) + 0.5f) * inv_n);
+          const T x = X[t * g.pitch + (f - t * n)];
+          if (a.update) d64[base + f] = old[i] + double(x) - shift;
+          else if (a.dst_f64) d64[base + f] = double(x);
+          else d32[base + f] = float(x);
+        }
+      }
+    } else {
+      const int t = tid % TL;
+      const int64_t l = l0 + t;
+      if (l < a.nlines) {
+        const int64_t base = (l / B) * (int64_t(n) * B) + (l % B);
+        double old[ELD];
         if (a.update) {
-          double* d = static_cast<double*>(a.dst);
-          d[o] = d[o] + double(x) - (a.shift ? a.shift[0] : 0.0);
-        } else if (a.dst_f64) {
-          static_cast<double*>(a.dst)[o] = double(x);
-        } else {
-          static_cast<float*>(a.dst)[o] = float(x);
+#pragma unroll
+          for (int i = 0; i < ELD; ++i) {
+            const int j = tid / TL + i * (NT / TL);
+            old[i] = j < n ? d64[base + int64_t(j) * B] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < ELD; ++i) {
+          const int j = tid / TL + i * (NT / TL);
+          if (j < n) {
+            const T x = X[j * TL + t];
+            const int64_t o = base + int64_t(j) * B;
+            if (a.update) d64[o] = old[i] + double(x) - shift;
+            else if (a.dst_f64) d64[o] = double(x);
+            else d32[o] = float(x);
+          }
         }
       }
     }
