@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpois.so")
 SOURCES = ["aux.hip", "dispatch.cpp", "mpois.cpp", "tune.cpp"]
-NUM_SHAPES = 11  # entries of cfgs.h; lp_inst.hip is compiled once per shape
+NUM_SHAPES = 16  # entries of cfgs.h (MPOIS_NUM_CFGS); lp_inst.hip is compiled once per shape
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in device code

@@ -397,7 +397,7 @@ __device__ __forceinline__ void stage_rader(cx<T>* Z, int P, int ns, const cx<T>
 }
 
 // Forward DFT of length P of every pair column of Z.
-template <typename T, int NP, int NT, int PMAX, int RADER>
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
 __device__ __forceinline__ void dft_engine(cx<T>* Z, int P, int nstages, const Stage* __restrict__ stp,
                                            const cx<T>* __restrict__ tw, const cx<T>* __restrict__ cs) {
   for (int s = 0; s < nstages; ++s) {
@@ -411,12 +411,17 @@ __device__ __forceinline__ void dft_engine(cx<T>* Z, int P, int nstages, const S
       case 7: stage<T, 7, NP, NT, PMAX>(Z, P, st.ns, t); break;
       case 8: stage<T, 8, NP, NT, PMAX>(Z, P, st.ns, t); break;
       case 9: stage<T, 9, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 11: stage<T, 11, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 13: stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 11:
+        if constexpr (SLIM == 0) stage<T, 11, NP, NT, PMAX>(Z, P, st.ns, t);
+        break;
+      case 13:
+        if constexpr (SLIM == 0) stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t);
+        break;
       case 16: stage<T, 16, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 32: stage<T, 32, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 64:
-        if constexpr (sizeof(T) == 4) stage<T, 64, NP, NT, PMAX>(Z, P, st.ns, t);
+      case 32:
+        // largest power-of-two codelet: 32 in FP32 only (keeps FP64 threads
+        // near 100 registers, so two workgroups share a CU)
+        if constexpr (sizeof(T) == 4) stage<T, 32, NP, NT, PMAX>(Z, P, st.ns, t);
         break;
       case 73:
         if constexpr (RADER != 0) stage_rader<T, 73, NP, NT, PMAX>(Z, P, st.ns, t, cs + st.cs_off);
@@ -691,7 +696,7 @@ __device__ __forceinline__ int64_t xcd_tile(unsigned b, unsigned G) {
   return int64_t(x) * q + (x < r ? x : r) + i;
 }
 
-template <typename T, int NP, int NT, int PMAX, int RADER>
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
 __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, unsigned char* smem) {
   constexpr int TL = 2 * NP;
   T* X = reinterpret_cast<T*>(smem);
@@ -704,30 +709,33 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
   g.contiguous = (B == 1);
   g.pitch = n | 1;
 
-  // ---- load.  Every element of the tile is requested before any is written
-  // to LDS, so the whole tile (tens of KB per workgroup) is in flight at once.
+  // ---- load.  Elements are requested in chunks of CH per thread, all CH
+  // before any LDS write, so a 16-line tile of 512 doubles is in flight at once.
   constexpr int ELD = (2 * NP * PMAX + NT - 1) / NT;  // bound for n <= PMAX
+  constexpr int CH = ELD < 16 ? ELD : 16;
   {
     const int tid = opaque_tid();
-    T ld[ELD];
     if (g.contiguous) {
       const int64_t lend = (l0 + TL < a.nlines) ? l0 + TL : a.nlines;
       const int valid = int((lend - l0) * n);
       const int64_t base = l0 * n;
-#pragma unroll
-      for (int i = 0; i < ELD; ++i) {
-        const int f = tid + i * NT;
-        ld[i] = (f < valid) ? load_elem<T>(a.src, base + f, a.src_f64) : T(0);
-      }
       // t = f / n without an integer division: f < 2^18 and n <= 8192 keep the
       // float quotient at least 1/(2n) away from the next integer.
       const float inv_n = 1.0f / float(n);
+      for (int c = 0; c < ELD && c * NT < TL * n; c += CH) {
+        T ld[CH];
 #pragma unroll
-      for (int i = 0; i < ELD; ++i) {
-        const int f = tid + i * NT;
-        if (f < TL * n) {
-          const int t = int((float(f) + 0.5f) * inv_n);
-          X[t * g.pitch + (f - t * n)] = ld[i];
+        for (int i = 0; i < CH; ++i) {
+          const int f = tid + (c + i) * NT;
+          ld[i] = (f < valid) ? load_elem<T>(a.src, base + f, a.src_f64) : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int f = tid + (c + i) * NT;
+          if (f < TL * n) {
+            const int t = int((float(f) + 0.5f) * inv_n);
+            X[t * g.pitch + (f - t * n)] = ld[i];
+          }
         }
       }
     } else {
@@ -735,15 +743,18 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
       const int64_t l = l0 + t;
       const bool ok = l < a.nlines;
       const int64_t base = ok ? (l / B) * (int64_t(n) * B) + (l % B) : 0;
+      for (int c = 0; c < ELD && c * (NT / TL) < n; c += CH) {
+        T ld[CH];
 #pragma unroll
-      for (int i = 0; i < ELD; ++i) {
-        const int j = tid / TL + i * (NT / TL);
-        ld[i] = (ok && j < n) ? load_elem<T>(a.src, base + int64_t(j) * B, a.src_f64) : T(0);
-      }
+        for (int i = 0; i < CH; ++i) {
+          const int j = tid / TL + (c + i) * (NT / TL);
+          ld[i] = (ok && j < n) ? load_elem<T>(a.src, base + int64_t(j) * B, a.src_f64) : T(0);
+        }
 #pragma unroll
-      for (int i = 0; i < ELD; ++i) {
-        const int j = tid / TL + i * (NT / TL);
-        if (j < n) X[j * TL + t] = ld[i];
+        for (int i = 0; i < CH; ++i) {
+          const int j = tid / TL + (c + i) * (NT / TL);
+          if (j < n) X[j * TL + t] = ld[i];
+        }
       }
     }
   }
@@ -768,12 +779,12 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
         for (int item = threadIdx.x; item < items; item += NT) Z[item] = conj(cmul(Z[item], bh[item / NP]));
         __syncthreads();
       }
-      dft_engine<T, NP, NT, PMAX, RADER>(Z, ax.P, ax.nstages, ax.st, tw, cs);
+      dft_engine<T, NP, NT, PMAX, RADER, SLIM>(Z, ax.P, ax.nstages, ax.st, tw, cs);
     }
     unpack<T, NP, NT, PMAX>(Z, X, g, kind, ax, a, l0, phase == 0 && nphase == 2);
   }
 
-  // ---- store (in update mode the old values are all requested first)
+  // ---- store (in update mode the old values of a chunk are requested first)
   {
     const int tid = opaque_tid();
     const double shift = (a.update && a.shift) ? a.shift[0] : 0.0;
@@ -784,23 +795,25 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
       const int valid = int((lend - l0) * n);
       const int64_t base = l0 * n;
       const float inv_n = 1.0f / float(n);
-      double old[ELD];
-      if (a.update) {
+      for (int c = 0; c < ELD && c * NT < valid; c += CH) {
+        double old[CH];
+        if (a.update) {
 #pragma unroll
-        for (int i = 0; i < ELD; ++i) {
-          const int f = tid + i * NT;
-          old[i] = f < valid ? d64[base + f] : 0.0;
+          for (int i = 0; i < CH; ++i) {
+            const int f = tid + (c + i) * NT;
+            old[i] = f < valid ? d64[base + f] : 0.0;
+          }
         }
-      }
 #pragma unroll
-      for (int i = 0; i < ELD; ++i) {
-        const int f = tid + i * NT;
-        if (f < valid) {
-          const int t = int((float(f) + 0.5f) * inv_n);
-          const T x = X[t * g.pitch + (f - t * n)];
-          if (a.update) d64[base + f] = old[i] + double(x) - shift;
-          else if (a.dst_f64) d64[base + f] = double(x);
-          else d32[base + f] = float(x);
+        for (int i = 0; i < CH; ++i) {
+          const int f = tid + (c + i) * NT;
+          if (f < valid) {
+            const int t = int((float(f) + 0.5f) * inv_n);
+            const T x = X[t * g.pitch + (f - t * n)];
+            if (a.update) d64[base + f] = old[i] + double(x) - shift;
+            else if (a.dst_f64) d64[base + f] = double(x);
+            else d32[base + f] = float(x);
+          }
         }
       }
     } else {
@@ -808,23 +821,25 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
       const int64_t l = l0 + t;
       if (l < a.nlines) {
         const int64_t base = (l / B) * (int64_t(n) * B) + (l % B);
-        double old[ELD];
-        if (a.update) {
+        for (int c = 0; c < ELD && c * (NT / TL) < n; c += CH) {
+          double old[CH];
+          if (a.update) {
 #pragma unroll
-          for (int i = 0; i < ELD; ++i) {
-            const int j = tid / TL + i * (NT / TL);
-            old[i] = j < n ? d64[base + int64_t(j) * B] : 0.0;
+            for (int i = 0; i < CH; ++i) {
+              const int j = tid / TL + (c + i) * (NT / TL);
+              old[i] = j < n ? d64[base + int64_t(j) * B] : 0.0;
+            }
           }
-        }
 #pragma unroll
-        for (int i = 0; i < ELD; ++i) {
-          const int j = tid / TL + i * (NT / TL);
-          if (j < n) {
-            const T x = X[j * TL + t];
-            const int64_t o = base + int64_t(j) * B;
-            if (a.update) d64[o] = old[i] + double(x) - shift;
-            else if (a.dst_f64) d64[o] = double(x);
-            else d32[o] = float(x);
+          for (int i = 0; i < CH; ++i) {
+            const int j = tid / TL + (c + i) * (NT / TL);
+            if (j < n) {
+              const T x = X[j * TL + t];
+              const int64_t o = base + int64_t(j) * B;
+              if (a.update) d64[o] = old[i] + double(x) - shift;
+              else if (a.dst_f64) d64[o] = double(x);
+              else d32[o] = float(x);
+            }
           }
         }
       }
@@ -833,18 +848,27 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
 }
 
 
+// Waves per SIMD the compiler must leave room for: 4 for slim shapes (two
+// 512-thread workgroups per CU, at most 128 registers per thread), else 1.
+template <int SLIM>
+struct MinWaves {
+  static constexpr int v = SLIM ? 4 : 1;
+};
+
 // One grid: block b owns tile b.
-template <typename T, int NP, int NT, int PMAX, int RADER>
-__global__ void __launch_bounds__(NT) line_pass(PassArgs a) {
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM>::v, 8)))
+line_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  line_pass_body<T, NP, NT, PMAX, RADER>(a, xcd_tile(blockIdx.x, gridDim.x), smem);
+  line_pass_body<T, NP, NT, PMAX, RADER, SLIM>(a, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
 // Many grids in one launch: block b works on tile tile_idx[b] of grid
 // tile_prob[b]; the per-grid pass description comes from a device table and
 // the array pointers from per-grid pointer tables.
-template <typename T, int NP, int NT, int PMAX, int RADER>
-__global__ void __launch_bounds__(NT) line_pass_batch(BatchPassArgs b) {
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM>::v, 8)))
+line_pass_batch(BatchPassArgs b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int pi = b.tile_prob[blockIdx.x];
   PassArgs a = b.args[pi];
@@ -854,29 +878,29 @@ __global__ void __launch_bounds__(NT) line_pass_batch(BatchPassArgs b) {
   a.dst_f64 = b.dst_f64;
   a.update = b.update;
   a.shift = (b.update && b.shift_base && a.singular) ? b.shift_base + int64_t(pi) * b.shift_stride : nullptr;
-  line_pass_body<T, NP, NT, PMAX, RADER>(a, int64_t(b.tile_idx[blockIdx.x]), smem);
+  line_pass_body<T, NP, NT, PMAX, RADER, SLIM>(a, int64_t(b.tile_idx[blockIdx.x]), smem);
 }
 
-template <typename T, int NP, int NT, int PMAX, int RADER>
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
 hipError_t launch_lp(const PassArgs& a, hipStream_t s, size_t lds) {
   constexpr int64_t TL = 2 * NP;
   const int64_t blocks = (a.nlines + TL - 1) / TL;
-  hipLaunchKernelGGL((line_pass<T, NP, NT, PMAX, RADER>), dim3(unsigned(blocks)), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((line_pass<T, NP, NT, PMAX, RADER, SLIM>), dim3(unsigned(blocks)), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int NP, int NT, int PMAX, int RADER>
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
 hipError_t launch_lp_batch(const BatchPassArgs& b, int blocks, hipStream_t s, size_t lds) {
-  hipLaunchKernelGGL((line_pass_batch<T, NP, NT, PMAX, RADER>), dim3(unsigned(blocks)), dim3(NT), lds, s, b);
+  hipLaunchKernelGGL((line_pass_batch<T, NP, NT, PMAX, RADER, SLIM>), dim3(unsigned(blocks)), dim3(NT), lds, s, b);
   return hipGetLastError();
 }
 
-template <typename T, int NP, int NT, int PMAX, int RADER>
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
 hipError_t prepare_lp() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass<T, NP, NT, PMAX, RADER>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass<T, NP, NT, PMAX, RADER, SLIM>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass_batch<T, NP, NT, PMAX, RADER>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass_batch<T, NP, NT, PMAX, RADER, SLIM>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 

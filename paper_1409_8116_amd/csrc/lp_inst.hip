@@ -14,8 +14,8 @@ namespace mpois {
 #define MPOIS_PASTE(a, b) MPOIS_PASTE2(a, b)
 
 hipError_t MPOIS_PASTE(launch_line_pass_cfg, MPOIS_CFG)(const PassArgs& a, hipStream_t s, size_t lds) {
-#define X(ID, T, NP, NT, PMAX, RADER) \
-  if constexpr (ID == MPOIS_CFG) return launch_lp<T, NP, NT, PMAX, RADER>(a, s, lds);
+#define X(ID, T, NP, NT, PMAX, RADER, SLIM) \
+  if constexpr (ID == MPOIS_CFG) return launch_lp<T, NP, NT, PMAX, RADER, SLIM>(a, s, lds);
   MPOIS_CFGS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -23,16 +23,16 @@ hipError_t MPOIS_PASTE(launch_line_pass_cfg, MPOIS_CFG)(const PassArgs& a, hipSt
 
 hipError_t MPOIS_PASTE(launch_line_pass_batch_cfg, MPOIS_CFG)(const BatchPassArgs& b, int blocks, hipStream_t s,
                                                              size_t lds) {
-#define X(ID, T, NP, NT, PMAX, RADER) \
-  if constexpr (ID == MPOIS_CFG) return launch_lp_batch<T, NP, NT, PMAX, RADER>(b, blocks, s, lds);
+#define X(ID, T, NP, NT, PMAX, RADER, SLIM) \
+  if constexpr (ID == MPOIS_CFG) return launch_lp_batch<T, NP, NT, PMAX, RADER, SLIM>(b, blocks, s, lds);
   MPOIS_CFGS(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
 hipError_t MPOIS_PASTE(prepare_line_pass_cfg, MPOIS_CFG)() {
-#define X(ID, T, NP, NT, PMAX, RADER) \
-  if constexpr (ID == MPOIS_CFG) return prepare_lp<T, NP, NT, PMAX, RADER>();
+#define X(ID, T, NP, NT, PMAX, RADER, SLIM) \
+  if constexpr (ID == MPOIS_CFG) return prepare_lp<T, NP, NT, PMAX, RADER, SLIM>();
   MPOIS_CFGS(X)
 #undef X
   return hipErrorInvalidValue;

@@ -24,6 +24,7 @@ namespace mpois {
 int num_kernel_cfgs();
 void kernel_cfg(int i, int* f64, int* np, int* nt, int* pmax);
 int kernel_cfg_rader(int i);
+int kernel_cfg_slim(int i);
 size_t line_pass_lds(int cfg, int n, int P);
 hipError_t prepare_kernels();
 hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s);
@@ -119,17 +120,23 @@ void axis_eigs(int bc, int grid, int approx, int64_t n, double h, double* out) {
 // Stockham stages for a DFT of length M: a Rader stage for the prime 73 first
 // (only for work lengths up to 1024, where its kernels are instantiated), then
 // the odd codelet radices, then the power-of-two part split into as few,
-// as even radices as the register budget allows (at most 32 in FP64, 64 in
+// as even radices as the register budget allows (at most 16 in FP64, 32 in
 // FP32).  Returns false if a prime the codelets do not cover remains.
 constexpr int kRaderPrime = 73;
-bool factor_radices(int64_t M, bool f64, bool allow_rader, std::vector<int>* out) {
+bool factor_radices(int64_t M, bool f64, bool exact, std::vector<int>* out) {
   out->clear();
   int64_t m = M;
-  if (allow_rader && M <= 1024 && m % kRaderPrime == 0) {
+  if (exact && M <= 1024 && m % kRaderPrime == 0) {
     out->push_back(kRaderPrime);
     m /= kRaderPrime;
   }
-  for (int r : {9, 3, 5, 7, 11, 13}) {
+  // Bluestein lengths are chosen 7-smooth, so they run in every kernel shape
+  static const int kOddExact[] = {9, 3, 5, 7, 11, 13};
+  static const int kOddSmooth[] = {9, 3, 5, 7};
+  const int* odd = exact ? kOddExact : kOddSmooth;
+  const int nodd = exact ? 6 : 4;
+  for (int oi = 0; oi < nodd; ++oi) {
+    const int r = odd[oi];
     while (m % r == 0) {
       out->push_back(r);
       m /= r;
@@ -141,7 +148,7 @@ bool factor_radices(int64_t M, bool f64, bool allow_rader, std::vector<int>* out
     ++e;
   }
   if (m != 1) return false;
-  const int emax = f64 ? 5 : 6;
+  const int emax = f64 ? 4 : 5;  // radix <= 16 in FP64, <= 32 in FP32 (register budget)
   if (e > 0) {
     const int nst = (e + emax - 1) / emax;
     for (int i = 0; i < nst; ++i) {
@@ -206,6 +213,13 @@ AxisShape plan_axis_shape(int bc, int grid, int64_t n, bool f64) {
 bool has_rader(const AxisShape& s) {
   for (int r : s.radices)
     if (r == kRaderPrime) return true;
+  return false;
+}
+
+// Radix 11 or 13: only the full (non-slim) kernel shapes have those codelets.
+bool has_odd_large(const AxisShape& s) {
+  for (int r : s.radices)
+    if (r == 11 || r == 13) return true;
   return false;
 }
 
@@ -448,23 +462,33 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
   return MPOIS_OK;
 }
 
-// Kernel configuration for a line pass: the widest tile (most line pairs) of
-// the working precision that holds the work length in LDS.  The Rader stage is
-// compiled only into some shapes (work length <= 1024; in FP64 the 256-thread
-// ones, where one wave per SIMD leaves the whole register file for its ~300
-// live registers per thread).
-int default_cfg(bool f64, int n, int P, bool rader) {
-  int best = -1, best_np = 0, best_nt = 0;
+// Kernel configuration for a line pass.  Candidates: shapes of the working
+// precision that hold the work length in LDS and have the codelets the stage
+// list needs (the Rader stage only in RADER shapes; radix 11/13 only in
+// non-slim shapes).  Preference: slim shapes that fit two workgroups per CU
+// (LDS <= 80 KB), then the widest tile.  MPOIS_FLAG_TUNE replaces this guess
+// by a measurement.
+bool cfg_fits(int i, bool f64, int n, int P, bool rader, bool odd) {
+  int cf64, np, nt, pmax;
+  kernel_cfg(i, &cf64, &np, &nt, &pmax);
+  if ((cf64 != 0) != f64 || P > pmax) return false;
+  if (rader && !kernel_cfg_rader(i)) return false;
+  if (odd && kernel_cfg_slim(i)) return false;
+  return line_pass_lds(i, n, P) <= size_t(kMaxLds);
+}
+
+int default_cfg(bool f64, int n, int P, bool rader, bool odd) {
+  int best = -1;
+  long best_score = -1;
   for (int i = 0; i < num_kernel_cfgs(); ++i) {
+    if (!cfg_fits(i, f64, n, P, rader, odd)) continue;
     int cf64, np, nt, pmax;
     kernel_cfg(i, &cf64, &np, &nt, &pmax);
-    if ((cf64 != 0) != f64 || P > pmax) continue;
-    if (rader && !kernel_cfg_rader(i)) continue;
-    if (line_pass_lds(i, n, P) > size_t(kMaxLds)) continue;
-    if (np > best_np || (np == best_np && nt > best_nt)) {
+    const bool two = kernel_cfg_slim(i) && line_pass_lds(i, n, P) <= size_t(kMaxLds / 2);
+    const long score = (two ? 1000 : 0) + np * 10 + (nt == 512 ? 1 : 0);
+    if (score > best_score) {
       best = i;
-      best_np = np;
-      best_nt = nt;
+      best_score = score;
     }
   }
   return best;
@@ -502,7 +526,8 @@ mpois_status validate_one(const mpois_grid_desc* g, int approx, int prec, int ma
   // every axis must fit one of the kernel shapes
   for (int d = 0; d < g->ndim; ++d) {
     AxisShape s = plan_axis_shape(g->bc[d][0], g->grid[d], g->n[d], prec == MPOIS_F64);
-    if (default_cfg(prec == MPOIS_F64, int(g->n[d]), int(s.P), has_rader(s)) < 0) return MPOIS_ERR_UNSUPPORTED;
+    if (default_cfg(prec == MPOIS_F64, int(g->n[d]), int(s.P), has_rader(s), has_odd_large(s)) < 0)
+      return MPOIS_ERR_UNSUPPORTED;
   }
   return MPOIS_OK;
 }
@@ -605,9 +630,9 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
       }
     }
     p.axis = d;
-    p.cfg = default_cfg(pl->f64work, int(g->n[d]), int(at.shape.P), has_rader(at.shape));
-    if (tune_enabled(pl->flags) && p.cfg >= 0)
-      p.cfg = tune_pass(a, p.cfg, pl->f64work, has_rader(at.shape), size_t(kMaxLds));
+    const bool rader = has_rader(at.shape), odd = has_odd_large(at.shape);
+    p.cfg = default_cfg(pl->f64work, int(g->n[d]), int(at.shape.P), rader, odd);
+    if (tune_enabled(pl->flags) && p.cfg >= 0) p.cfg = tune_pass(a, p.cfg, pl->f64work, rader, odd);
     return p;
   };
   for (int d = D - 1; d >= 1; --d) sp->passes.push_back(axis_pass(d, false, false));

@@ -23,6 +23,7 @@ namespace mpois {
 int num_kernel_cfgs();
 void kernel_cfg(int i, int* f64, int* np, int* nt, int* pmax);
 int kernel_cfg_rader(int i);
+int kernel_cfg_slim(int i);
 size_t line_pass_lds(int cfg, int n, int P);
 hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s);
 
@@ -67,17 +68,18 @@ void save_entry(const std::string& key, int cfg) {
   if (out) out << device_name() << " " << key << " " << cfg << "\n";
 }
 
-bool fits(int cfg, bool f64, int n, int P, bool rader, size_t max_lds) {
+bool fits(int cfg, bool f64, int n, int P, bool rader, bool odd) {
   int cf64, np, nt, pmax;
   kernel_cfg(cfg, &cf64, &np, &nt, &pmax);
   if ((cf64 != 0) != f64 || P > pmax) return false;
   if (rader && !kernel_cfg_rader(cfg)) return false;
-  return line_pass_lds(cfg, n, P) <= max_lds;
+  if (odd && kernel_cfg_slim(cfg)) return false;
+  return line_pass_lds(cfg, n, P) <= size_t(160 * 1024);
 }
 
 }  // namespace
 
-int tune_pass(const PassArgs& proto, int fallback, bool f64, bool rader, size_t max_lds) {
+int tune_pass(const PassArgs& proto, int fallback, bool f64, bool rader, bool odd) {
   const int n = proto.ax.n, P = proto.ax.P;
   std::ostringstream k;
   k << (f64 ? "f64" : "f32") << "/kf" << proto.kind_f << "/kb" << proto.kind_b << "/n" << n << "/P" << P << "/lines"
@@ -86,11 +88,11 @@ int tune_pass(const PassArgs& proto, int fallback, bool f64, bool rader, size_t 
   std::lock_guard<std::mutex> lock(g_mu);
   load_file();
   auto it = g_cache.find(key);
-  if (it != g_cache.end() && fits(it->second, f64, n, P, rader, max_lds)) return it->second;
+  if (it != g_cache.end() && fits(it->second, f64, n, P, rader, odd)) return it->second;
 
   std::vector<int> cands;
   for (int i = 0; i < num_kernel_cfgs(); ++i)
-    if (fits(i, f64, n, P, rader, max_lds)) cands.push_back(i);
+    if (fits(i, f64, n, P, rader, odd)) cands.push_back(i);
   if (cands.size() <= 1) return cands.empty() ? fallback : cands[0];
 
   // scratch arrays of the pass's own size (values do not affect the timing)

@@ -1,7 +1,5 @@
 // Kernel-shape autotuner interface.
 #pragma once
-#include <cstddef>
-
 #include "internal.h"
 
 namespace mpois {
@@ -9,5 +7,5 @@ bool tune_enabled(unsigned flags);
 // Fastest kernel shape for one line pass (measured on scratch arrays of the
 // pass's size, or taken from the per-process / MPOIS_TUNE_CACHE cache);
 // `fallback` if nothing can be measured.
-int tune_pass(const PassArgs& proto, int fallback, bool f64, bool rader, size_t max_lds);
+int tune_pass(const PassArgs& proto, int fallback, bool f64, bool rader, bool odd);
 }  // namespace mpois

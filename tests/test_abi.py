@@ -111,7 +111,7 @@ def test_axis_plans(mp):
     p = mp.axis_plan("P", "v", 1021)  # prime: chirp convolution
     assert p["P"] >= 2 * 1021 - 1 and int(np.prod(p["radices"])) == p["P"]
     p = mp.axis_plan("D", "v", 1024)  # M = 2050 = 2 * 5^2 * 41
-    assert p["M"] == 2050 and p["P"] >= 4099 and set(p["radices"]) <= {2, 4, 8, 16, 32, 3, 9, 5, 7, 11, 13}
+    assert p["M"] == 2050 and p["P"] >= 4099 and set(p["radices"]) <= {2, 4, 8, 16, 3, 9, 5, 7, 11, 13}
     p = mp.axis_plan("N", "v", 512)  # 1022 = 2 * 7 * 73: Rader stage, no convolution
     assert p["P"] == 1022 and p["radices"][0] == 73
     for n in range(1, 300):
