@@ -75,28 +75,38 @@ __device__ __forceinline__ double second_diff_reg(double lo_v, double c, double 
 }
 
 // Block `blk` of `nblk` over one grid.  The work unit is a strip of RESID_NT
-// consecutive points along axis 2 at a fixed axis-1 index; the block marches
-// the strip along axis 0 keeping the axis-0 neighbours in registers, so each
-// value of phi comes from memory about once.  Writes the 4 block partial sums
-// to part[0..3].
+// consecutive points along axis 2, at a fixed axis-1 index, over a segment of
+// RESID_SEG planes of axis 0.  The block marches the segment along axis 0 with
+// the axis-0 neighbours in registers, so each value of phi comes from memory
+// about once (plus one halo plane per segment); short segments give many
+// independent workgroups to hide memory latency.
+constexpr int RESID_SEG = 32;
+
 __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int64_t nblk, double* part) {
   const int64_t n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
   const int64_t strips = (n2 + RESID_NT - 1) / RESID_NT;
-  const int64_t units = strips * n1;
+  const int64_t segs = (n0 + RESID_SEG - 1) / RESID_SEG;
+  const int64_t units = strips * n1 * segs;
   const int64_t plane = n1 * n2;
   const double mg = a.mg ? a.mg[0] : 0.0;
   double s_wphi = 0.0, s_wg = 0.0, s_r2 = 0.0, s_g2 = 0.0;
   for (int64_t u = blk; u < units; u += nblk) {
-    const int64_t i1 = u / strips;
-    const int64_t i2 = (u - i1 * strips) * RESID_NT + threadIdx.x;
+    const int64_t seg = u / (strips * n1);
+    const int64_t rem = u - seg * strips * n1;
+    const int64_t i1 = rem / strips;
+    const int64_t i2 = (rem - i1 * strips) * RESID_NT + threadIdx.x;
     if (i2 >= n2) continue;
     const int64_t base = i1 * n2 + i2;
     const double w12 = axis_weight(a.clo[1], i1, n1) * axis_weight(a.clo[2], i2, n2);
     const double first = a.phi[base];
     const double last = a.phi[base + (n0 - 1) * plane];
-    double prev = 0.0, cur = first;
-    double next = n0 > 1 ? a.phi[base + plane] : first;
-    for (int64_t i0 = 0; i0 < n0; ++i0) {
+    const int64_t s0 = seg * RESID_SEG;
+    const int64_t s1 = (s0 + RESID_SEG < n0) ? s0 + RESID_SEG : n0;
+    double prev = s0 > 0 ? a.phi[base + (s0 - 1) * plane] : 0.0;
+    double cur = a.phi[base + s0 * plane];
+    double next = s0 + 1 < n0 ? a.phi[base + (s0 + 1) * plane] : cur;
+#pragma unroll 4
+    for (int64_t i0 = s0; i0 < s1; ++i0) {
       const int64_t idx = i0 * plane + base;
       const double gv = a.g[idx];
       const double lap = a.inv_h2[2] * second_diff(a.phi, idx, i2, n2, 1, a.clo[2], cur) +
@@ -195,10 +205,12 @@ __global__ void zero_kernel(double* p, int64_t count) {
 }
 
 
-// Blocks of one residual launch: one per (axis-1 index, strip of axis 2), at most 4096.
+// Blocks of one residual launch: one per (axis-1 index, strip of axis 2,
+// segment of axis 0), at most 16384.
 int resid_blocks(const int64_t n[3]) {
-  const int64_t units = n[1] * ((n[2] + RESID_NT - 1) / RESID_NT);
-  return int(units < 4096 ? units : 4096);
+  const int64_t units =
+      n[1] * ((n[2] + RESID_NT - 1) / RESID_NT) * ((n[0] + RESID_SEG - 1) / RESID_SEG);
+  return int(units < 16384 ? units : 16384);
 }
 
 hipError_t launch_resid(const ResidArgs& a, hipStream_t s) {

@@ -43,7 +43,7 @@ using namespace mpois;
 namespace {
 
 constexpr int kMaxLds = 160 * 1024;
-constexpr int kMaxResidBlocks = 4096;
+constexpr int kMaxResidBlocks = 16384;
 const int kRadices[] = {8, 4, 2, 3, 5, 7, 11, 13};
 
 // ---------------------------------------------------------------------------- exact angles
@@ -851,7 +851,7 @@ mpois_status build_batch(mpois_plan_s* pl) {
     rargs[i] = sp.resid;
     rargs[i].singular = sp.singular ? 1 : 0;
     B.any_singular = B.any_singular || sp.singular;
-    const int64_t units = sp.n[1] * ((sp.n[2] + 255) / 256);  // residual work units (strips)
+    const int64_t units = sp.n[1] * ((sp.n[2] + 255) / 256) * ((sp.n[0] + 31) / 32);  // residual work units
     int64_t nb = (sp.npts + 8191) / 8192;
     nb = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(nb, 256), units));
     blk_start[i] = int(blk_prob.size());
