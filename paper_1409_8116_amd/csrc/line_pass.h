@@ -125,25 +125,6 @@ constexpr long ct_powmod(long b, long e, long m) {
 // Smallest primitive root of a prime p (declared below the tables that use it).
 constexpr long ct_primroot(long p);
 
-// Rader index tables of a prime R: gq[q] = g^q mod R, gi[m] = g^{-m} mod R.
-template <int R>
-struct RaderTable {
-  int gq[R - 1];
-  int gi[R - 1];
-  constexpr RaderTable() : gq(), gi() {
-    const long g = ct_primroot(R);
-    const long ginv = ct_powmod(g, R - 2, R);
-    for (int q = 0; q < R - 1; ++q) {
-      gq[q] = int(ct_powmod(g, q, R));
-      gi[q] = int(ct_powmod(ginv, q, R));
-    }
-  }
-};
-template <int R>
-struct Rader {
-  static constexpr RaderTable<R> t{};
-};
-
 constexpr long ct_primroot(long p) {
   for (long g = 2; g < p; ++g) {
     bool ok = true;
@@ -284,6 +265,8 @@ __device__ __forceinline__ void dft_any(cx<T>* v) {
   else if constexpr (R == 8) dft8(v);
   else if constexpr (R == 9) dft_2level<T, 3, 3>(v);
   else if constexpr (R == 16) dft_2level<T, 4, 4>(v);
+  else if constexpr (R == 18) dft_2level<T, 2, 9>(v);
+  else if constexpr (R == 36) dft_2level<T, 4, 9>(v);
   else if constexpr (R == 32) dft_2level<T, 8, 4>(v);
   else if constexpr (R == 64) dft_2level<T, 8, 8>(v);
   else if constexpr (R == 72) dft_2level<T, 8, 9>(v);
@@ -335,62 +318,184 @@ __device__ __forceinline__ void stage(cx<T>* Z, int P, int ns, const cx<T>* __re
   __syncthreads();
 }
 
+// ----------------------------------------------------------------------------- lane-parallel Rader
+// Exchange of a value with lane (lane ^ mask), mask in {1, 2, 4}, through DPP
+// lane moves (no LDS traffic): quad permutations for 1 and 2, and for 4 the
+// mirror inside each group of 8 lanes (lane ^ 7) followed by lane ^ 3.
+template <int MASK>
+__device__ __forceinline__ int lane_xor_i32(int v) {
+  static_assert(MASK == 1 || MASK == 2 || MASK == 4, "lane mask");
+  if constexpr (MASK == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);  // [1,0,3,2]
+  else if constexpr (MASK == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);  // [2,3,0,1]
+  else {
+    const int m = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // half-row mirror
+    return __builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, true);           // [3,2,1,0]
+  }
+}
+
+template <int MASK>
+__device__ __forceinline__ float lane_xor(float v) {
+  return __int_as_float(lane_xor_i32<MASK>(__float_as_int(v)));
+}
+
+template <int MASK>
+__device__ __forceinline__ double lane_xor(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_xor_i32<MASK>(int(b & 0xffffffffLL));
+  const int hi = lane_xor_i32<MASK>(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+template <int MASK, typename T>
+__device__ __forceinline__ cx<T> lane_xor_cx(cx<T> v) {
+  return {lane_xor<MASK>(v.re), lane_xor<MASK>(v.im)};
+}
+
+// e^{-2 pi i j / (2h)} for j < h <= 4.
+template <typename T>
+__device__ __forceinline__ cx<T> w2h(int j, int h) {
+  const T r2 = T(0.70710678118654752440084436210484903928483593768847);
+  if (h == 1 || j == 0) return {T(1), T(0)};
+  if (h == 2 || j == 2) return {T(0), T(-1)};
+  return {j == 1 ? r2 : -r2, -r2};
+}
+
+// One radix-2 step of a DFT of length G spread over G lanes (one value per
+// lane, K independent columns).  DIF (first=false): top lane x + x', bottom
+// lane (x' - x) w.  DIT (first=true): top x + w x', bottom x' - w x.
+template <typename T, int K, int H, bool DIT>
+__device__ __forceinline__ void lane_radix2(cx<T>* x, int s) {
+  const bool top = (s & H) == 0;
+  const T sg = top ? T(1) : T(-1);
+  const cx<T> w = w2h<T>(s & (H - 1), H);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const cx<T> xp = lane_xor_cx<H>(x[k]);
+    if constexpr (!DIT) {
+      const cx<T> t = {xp.re + sg * x[k].re, xp.im + sg * x[k].im};
+      x[k] = (H == 1) ? t : cmul(t, top ? cx<T>{T(1), T(0)} : w);
+    } else {
+      // top: x + w x' ; bottom: x' - w x  ==  u + sg * (w v) with (u, v) = top ? (x, x') : (x', x)
+      const cx<T> u = top ? x[k] : xp, v = top ? xp : x[k];
+      const cx<T> wv = (H == 1) ? v : cmul(w, v);
+      x[k] = {u.re + sg * wv.re, u.im + sg * wv.im};
+    }
+  }
+}
+
+template <int G>
+__device__ __forceinline__ int lane_bitrev(int s) {
+  if constexpr (G == 2) return s;
+  else if constexpr (G == 4) return ((s & 1) << 1) | (s >> 1);
+  else return ((s & 1) << 2) | (s & 2) | ((s & 4) >> 2);
+}
+
 // Prime radix R by Rader's algorithm: with a primitive root g of R, the
 // non-zero outputs are X[g^{-m}] = v_0 + (a (*) d)_m, a cyclic convolution of
-// length R-1 of a_q = v[g^q] with d_j = e^{-2 pi i g^{-j} / R}.  It runs in
-// registers as DFT, pointwise product with dhat = DFT(d) / (R-1), and an
-// inverse DFT (conjugate, DFT, conjugate).  X[0] is the plain sum.
-template <typename T, int R, int NP, int NT, int PMAX>
-__device__ __forceinline__ void stage_rader(cx<T>* Z, int P, int ns, const cx<T>* __restrict__ tw,
-                                            const cx<T>* __restrict__ dhat) {
-  constexpr int L = R - 1;
-  constexpr int NB = ((PMAX / R) * NP + NT - 1) / NT;
+// length R-1 of a_q = v[g^q] with d_j = e^{-2 pi i g^{-j} / R}, computed as a
+// DFT, a pointwise product with dhat = DFT(d) / (R-1), and an inverse DFT
+// (conjugate, DFT, conjugate).  X[0] is the plain sum v_0 + A_0.
+//
+// Rader stage for R = 73 (R - 1 = 72) with G lanes per butterfly, G in {2, 4, 8}.
+// Lane s of a group holds the K = 72/G convolution inputs a[G j + s]; each
+// length-72 DFT is a K-point DFT in registers, a twiddle e^{-2 pi i s k1/72},
+// and a G-point DFT across the lanes (DPP moves).  The second DFT runs the
+// same steps in the opposite order, so no data goes through LDS between the
+// two.  tab holds dhat (72 values, DFT_72(d)/72) then e^{-2 pi i j/72}, j < 72.
+// Every lane of a round runs the arithmetic (idle groups on zeros) so each
+// lane move has its partner; rounds with no work at all are skipped.
+template <typename T, int NP, int NT, int PMAX, int G>
+__device__ __forceinline__ void stage_rader73(cx<T>* Z, int P, int ns, const cx<T>* __restrict__ tw,
+                                              const cx<T>* __restrict__ tab) {
+  static_assert(G == 2 || G == 4 || G == 8, "lanes per Rader butterfly");
+  constexpr int R = 73, L = 72, K = L / G;
+  constexpr int NBG = ((PMAX / R) * NP * G + NT - 1) / NT;
+  constexpr long g = ct_primroot(R);
+  constexpr int gG = int(ct_powmod(g, G, R));
+  constexpr long ginv = ct_powmod(g, R - 2, R);
+  constexpr int giG = int(ct_powmod(ginv, G, R));
+  const cx<T>* dhat = tab;
+  const cx<T>* w72 = tab + L;
   const int nbp = P / R;
   const int items = nbp * NP;
   const int tid = opaque_tid();
-  cx<T> out[NB][R];
+  const int s = tid & (G - 1);
+  int gs = 1, gis = 1;  // g^s and g^{-s} mod R
+  for (int e = 0; e < s; ++e) {
+    gs = int((long(gs) * g) % R);
+    gis = int((long(gis) * ginv) % R);
+  }
+  // one round: outputs stay in x; several rounds keep them in out
+  cx<T> out[NBG > 1 ? NBG : 1][NBG > 1 ? K : 1];
+  cx<T> out0[NBG];
+  cx<T> x[K];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const int item = tid + i * NT;
-    if (item < items) {
-      const int p = item % NP;
-      const int b = item / NP;
-      cx<T> v[R];
+  for (int i = 0; i < NBG; ++i) {
+    if (i * (NT / G) >= items) break;  // uniform over the block
+    const int item = tid / G + i * (NT / G);
+    const bool act = item < items;
+    const int p = act ? item % NP : 0;
+    const int b = act ? item / NP : 0;
+    const int k = b % ns;
+    int r = gs;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = Z[(b + r * nbp) * NP + p];
-      if (ns > 1) {
-        const int k = b % ns;
-        const cx<T>* w = tw + k * (R - 1);
+    for (int j = 0; j < K; ++j) {
+      cx<T> v = act ? Z[(b + r * nbp) * NP + p] : cx<T>{T(0), T(0)};
+      if (ns > 1 && act) v = cmul(v, tw[k * (R - 1) + r - 1]);
+      x[j] = v;
+      r = (r * gG) % R;
+    }
+    const cx<T> v0 = act ? Z[b * NP + p] : cx<T>{T(0), T(0)};
+    // forward length-72 DFT of a
+    dft_any<T, K>(x);
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r - 1]);
-      }
-      cx<T> sum = v[0];
+    for (int k1 = 1; k1 < K; ++k1) x[k1] = cmul(x[k1], w72[s * k1]);
 #pragma unroll
-      for (int r = 1; r < R; ++r) sum = sum + v[r];
-      cx<T> a[L];
+    for (int h = G / 2; h >= 1; h >>= 1) {
+      if (h == 4) lane_radix2<T, K, 4, false>(x, s);
+      if (h == 2) lane_radix2<T, K, 2, false>(x, s);
+      if (h == 1) lane_radix2<T, K, 1, false>(x, s);
+    }
+    // lane s holds A[k1 + K bitrev(s)]; X[0] = v0 + A[0] (lane 0, k1 = 0)
+    const int k2 = lane_bitrev<G>(s);
+    out0[i] = v0 + x[0];
 #pragma unroll
-      for (int q = 0; q < L; ++q) a[q] = v[Rader<R>::t.gq[q]];
-      dft_any<T, L>(a);
+    for (int k1 = 0; k1 < K; ++k1) x[k1] = conj(cmul(x[k1], dhat[k1 + K * k2]));
+    // second length-72 DFT: across lanes first (bit-reversed in, natural out)
 #pragma unroll
-      for (int q = 0; q < L; ++q) a[q] = conj(cmul(a[q], dhat[q]));
-      dft_any<T, L>(a);
-      out[i][0] = sum;
+    for (int h = 1; h <= G / 2; h <<= 1) {
+      if (h == 1) lane_radix2<T, K, 1, true>(x, s);
+      if (h == 2) lane_radix2<T, K, 2, true>(x, s);
+      if (h == 4) lane_radix2<T, K, 4, true>(x, s);
+    }
 #pragma unroll
-      for (int m = 0; m < L; ++m) out[i][Rader<R>::t.gi[m]] = v[0] + conj(a[m]);
+    for (int j2 = 1; j2 < K; ++j2) x[j2] = cmul(x[j2], w72[j2 * s]);
+    dft_any<T, K>(x);
+    // lane s holds conj(c[s + G kk]);  X[g^{-(s + G kk)}] = v0 + c
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) x[kk] = v0 + conj(x[kk]);
+    if constexpr (NBG > 1) {
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) out[i][kk] = x[kk];
     }
   }
   __syncthreads();
   const int tid2 = opaque_tid();
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const int item = tid2 + i * NT;
+  for (int i = 0; i < NBG; ++i) {
+    const int item = tid2 / G + i * (NT / G);
     if (item < items) {
       const int p = item % NP;
       const int b = item / NP;
       const int k = b % ns;
       const int base = (b - k) * R + k;
+      int oi = gis;
 #pragma unroll
-      for (int r = 0; r < R; ++r) Z[(base + r * ns) * NP + p] = out[i][r];
+      for (int kk = 0; kk < K; ++kk) {
+        Z[(base + oi * ns) * NP + p] = (NBG > 1) ? out[i][kk] : x[kk];
+        oi = (oi * giG) % R;
+      }
+      if (s == 0) Z[base * NP + p] = out0[i];
     }
   }
   __syncthreads();
@@ -424,7 +529,7 @@ __device__ __forceinline__ void dft_engine(cx<T>* Z, int P, int nstages, const S
         if constexpr (sizeof(T) == 4) stage<T, 32, NP, NT, PMAX>(Z, P, st.ns, t);
         break;
       case 73:
-        if constexpr (RADER != 0) stage_rader<T, 73, NP, NT, PMAX>(Z, P, st.ns, t, cs + st.cs_off);
+        if constexpr (RADER != 0) stage_rader73<T, NP, NT, PMAX, RADER>(Z, P, st.ns, t, cs + st.cs_off);
         break;
       default: break;  // the planner only emits the radices above
     }

@@ -418,6 +418,8 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
       }
       host_dft(d);
       for (auto& x : d) cs.push_back(x / double(L));
+      // twiddles e^{-2 pi i j / L} of the two-level length-L DFT
+      for (int j = 0; j < L; ++j) cs.emplace_back(cospi_frac(2 * j, L), -sinpi_frac(2 * j, L));
     }
     ns *= R;
   }
@@ -466,7 +468,8 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
 // precision that hold the work length in LDS and have the codelets the stage
 // list needs (the Rader stage only in RADER shapes; radix 11/13 only in
 // non-slim shapes).  Preference: slim shapes that fit two workgroups per CU
-// (LDS <= 80 KB), then the widest tile.  MPOIS_FLAG_TUNE replaces this guess
+// (LDS <= 80 KB), then the widest tile; with a Rader stage, 256 threads and
+// the narrowest tile.  MPOIS_FLAG_TUNE replaces this guess
 // by a measurement.
 bool cfg_fits(int i, bool f64, int n, int P, bool rader, bool odd) {
   int cf64, np, nt, pmax;
@@ -485,7 +488,9 @@ int default_cfg(bool f64, int n, int P, bool rader, bool odd) {
     int cf64, np, nt, pmax;
     kernel_cfg(i, &cf64, &np, &nt, &pmax);
     const bool two = kernel_cfg_slim(i) && line_pass_lds(i, n, P) <= size_t(kMaxLds / 2);
-    const long score = (two ? 1000 : 0) + np * 10 + (nt == 512 ? 1 : 0);
+    // a Rader stage keeps many values per lane: smaller workgroups and tiles
+    // leave the registers to it (measured fastest on 512^3 DCT-I passes)
+    const long score = rader ? (nt == 256 ? 100 : 0) - np : (two ? 1000 : 0) + np * 10 + (nt == 512 ? 1 : 0);
     if (score > best_score) {
       best = i;
       best_score = score;
