@@ -7,7 +7,7 @@
 
 #define MPOIS_CFGS_F64(X)          \
   X(0, double, 8, 512, 1024, 0, 1)  \
-  X(1, double, 8, 256, 1024, 4, 0)  \
+  X(1, double, 8, 512, 1024, 4, 0)  \
   X(2, double, 4, 256, 1024, 4, 0)  \
   X(3, double, 4, 512, 2048, 0, 1)  \
   X(4, double, 2, 512, 4096, 0, 1)  \

@@ -790,6 +790,51 @@ __device__ __forceinline__ void unpack(cx<T>* Z, T* X, const TileGeom& g, int ki
   }
 }
 
+// ----------------------------------------------------------------------------- strided-tile shortcuts
+// For a strided tile the real tile X[j * TL + t] and the packed work buffer
+// Z[m * NP + p] (line t = 2p + w in component w) are the same memory.  A
+// DCT-I input then only needs its even extension, rows m = n..M-1 copied from
+// rows M - m, and a DCT-I output is already in place.
+template <typename T, int NP, int NT>
+__device__ __forceinline__ void dct1_mirror(cx<T>* Z, int n, int M) {
+  const int items = (M - n) * NP;
+  for (int it = int(threadIdx.x); it < items; it += NT) {
+    const int m = n + it / NP, p = it % NP;
+    Z[m * NP + p] = Z[(M - m) * NP + p];
+  }
+  __syncthreads();
+}
+
+// In-place division of a DCT-I result by the eigenvalue sums, written to the
+// mirrored rows as well, so that the result is at once the input of the
+// inverse DCT-I.
+template <typename T, int NP, int NT>
+__device__ __forceinline__ void dct1_scale_mirror(T* X, const AxisDev& ax, const PassArgs& a, int64_t l0) {
+  constexpr int TL = 2 * NP;
+  static_assert(NT % TL == 0, "thread count must be a multiple of the tile width");
+  const int n = ax.n, M = ax.M;
+  const int tid = int(threadIdx.x);
+  const int t = tid % TL;
+  const int64_t l = l0 + t;
+  const T* la = static_cast<const T*>(a.lam_a);
+  const T* lb = static_cast<const T*>(a.lam_b);
+  const T* lt = static_cast<const T*>(a.lam_this);
+  T lam_other = T(0);
+  const bool dead_line = l >= a.nlines;
+  if (!dead_line) {
+    if (lb) lam_other = la[l / a.nb] + lb[l % a.nb];
+    else if (la) lam_other = la[l];
+  }
+  const bool zero_line = a.singular && (l == 0);
+  for (int it = tid; it < n * TL; it += NT) {
+    const int k = it / TL;
+    const T x = (dead_line || (zero_line && k == 0)) ? T(0) : X[it] / (lam_other + lt[k]);
+    X[it] = x;
+    if (k >= 1 && k <= n - 2) X[(M - k) * TL + t] = x;
+  }
+  __syncthreads();
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
 // b mod 8).  Give each XCD a contiguous range of tiles, so that neighbouring
 // tiles -- which share cache lines on the strided axes -- meet in the same L2.
@@ -873,9 +918,16 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
   const cx<T>* bh = static_cast<const cx<T>*>(ax.bhat);
   const int nphase = a.kind_b >= 0 ? 2 : 1;
   const int nrep = ax.bluestein ? 2 : 1;
+  // strided tiles without a chirp convolution take the in-place shortcuts
+  const bool inplace = !g.contiguous && !ax.bluestein;
+  bool mirrored = false;  // the middle step already built the DCT-I input
   for (int phase = 0; phase < nphase; ++phase) {
     const int kind = phase == 0 ? a.kind_f : a.kind_b;
-    pack<T, NP, NT, PMAX>(X, Z, g, kind, ax);
+    if (inplace && kind == K_DCT1) {
+      if (!mirrored) dct1_mirror<T, NP, NT>(Z, n, ax.M);
+    } else if (!(inplace && kind == K_R2HC)) {
+      pack<T, NP, NT, PMAX>(X, Z, g, kind, ax);
+    }
     // Stockham DFT; for Bluestein: DFT, times the kernel spectrum, conjugate, DFT
     // (the unpacker conjugates and applies the chirp).
     for (int rep = 0; rep < nrep; ++rep) {
@@ -886,7 +938,15 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
       }
       dft_engine<T, NP, NT, PMAX, RADER, SLIM>(Z, ax.P, ax.nstages, ax.st, tw, cs);
     }
-    unpack<T, NP, NT, PMAX>(Z, X, g, kind, ax, a, l0, phase == 0 && nphase == 2);
+    const bool scale = phase == 0 && nphase == 2;
+    if (inplace && kind == K_DCT1) {
+      if (scale) {
+        dct1_scale_mirror<T, NP, NT>(X, ax, a, l0);
+        mirrored = a.kind_b == K_DCT1;
+      }
+    } else {
+      unpack<T, NP, NT, PMAX>(Z, X, g, kind, ax, a, l0, scale);
+    }
   }
 
   // ---- store (in update mode the old values of a chunk are requested first)
@@ -954,15 +1014,18 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
 
 
 // Waves per SIMD the compiler must leave room for: 4 for slim shapes (two
-// 512-thread workgroups per CU, at most 128 registers per thread), else 1.
-template <int SLIM>
+// Waves per SIMD the compiler must leave room for: 4 for slim shapes (two
+// 512-thread workgroups per CU, at most 128 registers per thread), 2 for
+// shapes with the Rader stage (at most 256 registers, so that a second
+// workgroup can hide the first one's global memory latency), else 1.
+template <int SLIM, int RADER>
 struct MinWaves {
-  static constexpr int v = SLIM ? 4 : 1;
+  static constexpr int v = SLIM ? 4 : (RADER ? 2 : 1);
 };
 
 // One grid: block b owns tile b.
 template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM>::v, 8)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM, RADER>::v, 8)))
 line_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   line_pass_body<T, NP, NT, PMAX, RADER, SLIM>(a, xcd_tile(blockIdx.x, gridDim.x), smem);
@@ -972,7 +1035,7 @@ line_pass(PassArgs a) {
 // tile_prob[b]; the per-grid pass description comes from a device table and
 // the array pointers from per-grid pointer tables.
 template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM>::v, 8)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM, RADER>::v, 8)))
 line_pass_batch(BatchPassArgs b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int pi = b.tile_prob[blockIdx.x];

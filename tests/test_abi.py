@@ -115,7 +115,9 @@ def test_axis_plans(mp):
     p = mp.axis_plan("N", "v", 512)  # 1022 = 2 * 7 * 73: Rader stage, no convolution
     assert p["P"] == 1022 and p["radices"][0] == 73
     for n in range(1, 300):
-        for bc, grid in (("P", "v"), ("N", "s"), ("D", "v")):
+        for bc, grid in (("P", "v"), ("N", "s"), ("D", "v"), ("N", "v")):
+            if (bc, grid) == ("N", "v") and n < 2:
+                continue
             q = mp.axis_plan(bc, grid, n)
             assert int(np.prod(q["radices"])) == q["P"]
             assert q["P"] == q["M"] or q["P"] >= 2 * q["M"] - 1
