@@ -58,7 +58,7 @@ size_t line_pass_lds(int cfg, int n, int P) {
   const KernelCfg& c = kCfgs[cfg];
   const size_t es = c.f64 ? 8 : 4;
   const size_t tl = 2 * size_t(c.np);
-  const size_t xs = tl * size_t((n | 1) + 1);
+  const size_t xs = tl * size_t(n);
   const size_t zs = 2 * size_t(c.np) * size_t(P);
   return (xs > zs ? xs : zs) * es;
 }

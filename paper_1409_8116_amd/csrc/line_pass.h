@@ -1,9 +1,10 @@
 // Line-transform kernel of the fast Poisson solver for gfx950 (CDNA4).
 //
 // line_pass: one HBM sweep along one axis.  A workgroup owns a tile of TL = 2*NP
-// adjacent lines: it loads them into LDS with coalesced accesses (rows when the
-// axis is contiguous, TL-wide column segments when it is strided), packs two
-// real lines into one complex sequence per pair, runs a Stockham DFT over all
+// adjacent lines: it loads them into LDS with the lines innermost (TL-wide
+// segments of the TL lines per request), packs two real lines into one
+// complex sequence per pair (in place for the DCT-I and the real DFT, whose
+// packed layout is the tile layout itself), runs a Stockham DFT over all
 // pairs at once in LDS (or a Bluestein chirp convolution when the length has a
 // prime factor the codelets do not cover), unpacks, and stores.  The same
 // sweep can also apply the eigenvalue division and the inverse transform of
@@ -550,24 +551,21 @@ __device__ __forceinline__ T load_elem(const void* p, int64_t i, int f64) {
   return f64 ? T(static_cast<const double*>(p)[i]) : T(static_cast<const float*>(p)[i]);
 }
 
-// Real tile X: element (t, j) of line t of the tile.
-struct TileGeom {
-  int contiguous;  // 1: rows (inner == 1); 0: columns
-  int pitch;       // row pitch for contiguous tiles
-};
-
+// Real tile X: element j of line t of the tile at X[j * TL + t] (lines
+// innermost, for any axis), which is also the packed complex layout
+// Z[m * NP + p] with line t = 2p + w in component w.
 template <int TL>
-__device__ __forceinline__ int xi(const TileGeom& g, int t, int j) {
-  return g.contiguous ? t * g.pitch + j : j * TL + t;
+__device__ __forceinline__ int xi(int t, int j) {
+  return j * TL + t;
 }
 
 // Halfcomplex entry k (complex X_k) of a real DFT stored as h[0..n-1].
 template <typename T, int TL>
-__device__ __forceinline__ cx<T> hc_get(const T* X, const TileGeom& g, int t, int k, int n) {
-  if (k == 0) return {X[xi<TL>(g, t, 0)], T(0)};
-  if (2 * k < n) return {X[xi<TL>(g, t, k)], X[xi<TL>(g, t, n - k)]};
-  if (2 * k == n) return {X[xi<TL>(g, t, k)], T(0)};
-  return {X[xi<TL>(g, t, n - k)], -X[xi<TL>(g, t, k)]};
+__device__ __forceinline__ cx<T> hc_get(const T* X, int t, int k, int n) {
+  if (k == 0) return {X[xi<TL>(t, 0)], T(0)};
+  if (2 * k < n) return {X[xi<TL>(t, k)], X[xi<TL>(t, n - k)]};
+  if (2 * k == n) return {X[xi<TL>(t, k)], T(0)};
+  return {X[xi<TL>(t, n - k)], -X[xi<TL>(t, k)]};
 }
 
 // DCT-II reorder: v_m = x_{perm(m)} (even indices ascending, then odd descending).
@@ -578,40 +576,40 @@ __device__ __forceinline__ int perm_even_odd(int m, int n) {
 // Packing: the complex input of the length-M DFT for pair p at index m
 // (times the chirp for Bluestein, conjugated for inverse kinds).
 template <typename T, int TL, int kind>
-__device__ __forceinline__ cx<T> pack_value(const T* X, const TileGeom& g, const AxisDev& ax, int m, int p) {
+__device__ __forceinline__ cx<T> pack_value(const T* X, const AxisDev& ax, int m, int p) {
   const int n = ax.n, M = ax.M;
   const int t0 = 2 * p, t1 = 2 * p + 1;
   cx<T> val = {T(0), T(0)};
   if (m >= M) return val;
   switch (kind) {
     case K_R2HC:
-      val = {X[xi<TL>(g, t0, m)], X[xi<TL>(g, t1, m)]};
+      val = {X[xi<TL>(t0, m)], X[xi<TL>(t1, m)]};
       break;
     case K_DCT2:
     case K_DST2: {
       const int j = perm_even_odd(m, n);
-      val = {X[xi<TL>(g, t0, j)], X[xi<TL>(g, t1, j)]};
+      val = {X[xi<TL>(t0, j)], X[xi<TL>(t1, j)]};
       if (kind == K_DST2 && (j & 1)) val = {-val.re, -val.im};
       break;
     }
     case K_DCT1: {
       const int j = (m < n) ? m : M - m;
-      val = {X[xi<TL>(g, t0, j)], X[xi<TL>(g, t1, j)]};
+      val = {X[xi<TL>(t0, j)], X[xi<TL>(t1, j)]};
       break;
     }
     case K_DST1: {
       if (m == 0 || m == n + 1) break;
       if (m <= n) {
-        val = {X[xi<TL>(g, t0, m - 1)], X[xi<TL>(g, t1, m - 1)]};
+        val = {X[xi<TL>(t0, m - 1)], X[xi<TL>(t1, m - 1)]};
       } else {
         const int j = M - m - 1;
-        val = {-X[xi<TL>(g, t0, j)], -X[xi<TL>(g, t1, j)]};
+        val = {-X[xi<TL>(t0, j)], -X[xi<TL>(t1, j)]};
       }
       break;
     }
     case K_HC2R: {
-      const cx<T> a = hc_get<T, TL>(X, g, t0, m, n);
-      const cx<T> b = hc_get<T, TL>(X, g, t1, m, n);
+      const cx<T> a = hc_get<T, TL>(X, t0, m, n);
+      const cx<T> b = hc_get<T, TL>(X, t1, m, n);
       val = {a.re - b.im, -(a.im + b.re)};  // conj(a + i b)
       break;
     }
@@ -620,12 +618,12 @@ __device__ __forceinline__ cx<T> pack_value(const T* X, const TileGeom& g, const
       // V_k = e^{+i pi k/(2n)} (c_k - i c_{n-k}), c_n = 0; DST3 reverses c first.
       const int k = m;
       const int ka = (kind == K_DST3) ? n - 1 - k : k;
-      const T c0k = X[xi<TL>(g, t0, ka)], c1k = X[xi<TL>(g, t1, ka)];
+      const T c0k = X[xi<TL>(t0, ka)], c1k = X[xi<TL>(t1, ka)];
       T c0n = T(0), c1n = T(0);
       if (k > 0) {
         const int kb = (kind == K_DST3) ? k - 1 : n - k;
-        c0n = X[xi<TL>(g, t0, kb)];
-        c1n = X[xi<TL>(g, t1, kb)];
+        c0n = X[xi<TL>(t0, kb)];
+        c1n = X[xi<TL>(t1, kb)];
       }
       const cx<T> e = conj(static_cast<const cx<T>*>(ax.pre)[k]);
       const cx<T> v0 = cmul(e, cx<T>{c0k, -c0n});
@@ -689,7 +687,7 @@ __device__ __forceinline__ T unpack_value(const cx<T>* Z, const AxisDev& ax, int
 
 // X (real tile) -> Z (packed complex), through registers.
 template <typename T, int NP, int NT, int PMAX, int kind>
-__device__ __forceinline__ void pack_k(T* X, cx<T>* Z, const TileGeom& g, const AxisDev& ax) {
+__device__ __forceinline__ void pack_k(T* X, cx<T>* Z, const AxisDev& ax) {
   constexpr int TL = 2 * NP;
   constexpr int E = (PMAX * NP + NT - 1) / NT;
   const int items = ax.P * NP;
@@ -698,7 +696,7 @@ __device__ __forceinline__ void pack_k(T* X, cx<T>* Z, const TileGeom& g, const 
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int item = tid + i * NT;
-    if (item < items) v[i] = pack_value<T, TL, kind>(X, g, ax, item / NP, item % NP);
+    if (item < items) v[i] = pack_value<T, TL, kind>(X, ax, item / NP, item % NP);
   }
   __syncthreads();
   const int tid2 = opaque_tid();
@@ -711,22 +709,22 @@ __device__ __forceinline__ void pack_k(T* X, cx<T>* Z, const TileGeom& g, const 
 }
 
 template <typename T, int NP, int NT, int PMAX>
-__device__ __forceinline__ void pack(T* X, cx<T>* Z, const TileGeom& g, int kind, const AxisDev& ax) {
+__device__ __forceinline__ void pack(T* X, cx<T>* Z, int kind, const AxisDev& ax) {
   switch (kind) {
-    case K_R2HC: pack_k<T, NP, NT, PMAX, K_R2HC>(X, Z, g, ax); break;
-    case K_HC2R: pack_k<T, NP, NT, PMAX, K_HC2R>(X, Z, g, ax); break;
-    case K_DCT2: pack_k<T, NP, NT, PMAX, K_DCT2>(X, Z, g, ax); break;
-    case K_DCT3: pack_k<T, NP, NT, PMAX, K_DCT3>(X, Z, g, ax); break;
-    case K_DST2: pack_k<T, NP, NT, PMAX, K_DST2>(X, Z, g, ax); break;
-    case K_DST3: pack_k<T, NP, NT, PMAX, K_DST3>(X, Z, g, ax); break;
-    case K_DCT1: pack_k<T, NP, NT, PMAX, K_DCT1>(X, Z, g, ax); break;
-    default: pack_k<T, NP, NT, PMAX, K_DST1>(X, Z, g, ax); break;
+    case K_R2HC: pack_k<T, NP, NT, PMAX, K_R2HC>(X, Z, ax); break;
+    case K_HC2R: pack_k<T, NP, NT, PMAX, K_HC2R>(X, Z, ax); break;
+    case K_DCT2: pack_k<T, NP, NT, PMAX, K_DCT2>(X, Z, ax); break;
+    case K_DCT3: pack_k<T, NP, NT, PMAX, K_DCT3>(X, Z, ax); break;
+    case K_DST2: pack_k<T, NP, NT, PMAX, K_DST2>(X, Z, ax); break;
+    case K_DST3: pack_k<T, NP, NT, PMAX, K_DST3>(X, Z, ax); break;
+    case K_DCT1: pack_k<T, NP, NT, PMAX, K_DCT1>(X, Z, ax); break;
+    default: pack_k<T, NP, NT, PMAX, K_DST1>(X, Z, ax); break;
   }
 }
 
 // Z -> X, through registers, optionally dividing by the eigenvalue sum.
 template <typename T, int NP, int NT, int PMAX, int kind>
-__device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const TileGeom& g, const AxisDev& ax, const PassArgs& a,
+__device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const AxisDev& ax, const PassArgs& a,
                                          int64_t l0, bool scale) {
   constexpr int TL = 2 * NP;
   constexpr int E = (2 * PMAX * NP + NT - 1) / NT;
@@ -770,23 +768,23 @@ __device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const TileGeom& g, cons
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int item = tid2 + i * NT;
-    if (item < items) X[xi<TL>(g, tid2 % TL, item / TL)] = v[i];
+    if (item < items) X[xi<TL>(tid2 % TL, item / TL)] = v[i];
   }
   __syncthreads();
 }
 
 template <typename T, int NP, int NT, int PMAX>
-__device__ __forceinline__ void unpack(cx<T>* Z, T* X, const TileGeom& g, int kind, const AxisDev& ax,
+__device__ __forceinline__ void unpack(cx<T>* Z, T* X, int kind, const AxisDev& ax,
                                        const PassArgs& a, int64_t l0, bool scale) {
   switch (kind) {
-    case K_R2HC: unpack_k<T, NP, NT, PMAX, K_R2HC>(Z, X, g, ax, a, l0, scale); break;
-    case K_HC2R: unpack_k<T, NP, NT, PMAX, K_HC2R>(Z, X, g, ax, a, l0, scale); break;
-    case K_DCT2: unpack_k<T, NP, NT, PMAX, K_DCT2>(Z, X, g, ax, a, l0, scale); break;
-    case K_DCT3: unpack_k<T, NP, NT, PMAX, K_DCT3>(Z, X, g, ax, a, l0, scale); break;
-    case K_DST2: unpack_k<T, NP, NT, PMAX, K_DST2>(Z, X, g, ax, a, l0, scale); break;
-    case K_DST3: unpack_k<T, NP, NT, PMAX, K_DST3>(Z, X, g, ax, a, l0, scale); break;
-    case K_DCT1: unpack_k<T, NP, NT, PMAX, K_DCT1>(Z, X, g, ax, a, l0, scale); break;
-    default: unpack_k<T, NP, NT, PMAX, K_DST1>(Z, X, g, ax, a, l0, scale); break;
+    case K_R2HC: unpack_k<T, NP, NT, PMAX, K_R2HC>(Z, X, ax, a, l0, scale); break;
+    case K_HC2R: unpack_k<T, NP, NT, PMAX, K_HC2R>(Z, X, ax, a, l0, scale); break;
+    case K_DCT2: unpack_k<T, NP, NT, PMAX, K_DCT2>(Z, X, ax, a, l0, scale); break;
+    case K_DCT3: unpack_k<T, NP, NT, PMAX, K_DCT3>(Z, X, ax, a, l0, scale); break;
+    case K_DST2: unpack_k<T, NP, NT, PMAX, K_DST2>(Z, X, ax, a, l0, scale); break;
+    case K_DST3: unpack_k<T, NP, NT, PMAX, K_DST3>(Z, X, ax, a, l0, scale); break;
+    case K_DCT1: unpack_k<T, NP, NT, PMAX, K_DCT1>(Z, X, ax, a, l0, scale); break;
+    default: unpack_k<T, NP, NT, PMAX, K_DST1>(Z, X, ax, a, l0, scale); break;
   }
 }
 
@@ -855,40 +853,17 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
   const int n = ax.n;
   const int64_t B = a.inner;
   const int64_t l0 = tile * TL;
-  TileGeom g;
-  g.contiguous = (B == 1);
-  g.pitch = n | 1;
 
-  // ---- load.  Elements are requested in chunks of CH per thread, all CH
-  // before any LDS write, so a 16-line tile of 512 doubles is in flight at once.
+  // ---- load.  Thread (t, j0) reads elements j0, j0 + NT/TL, ... of line t:
+  // lines are innermost in LDS (conflict-free writes), and the TL lines of a
+  // contiguous axis are read TL at a time, their cache lines being reused by
+  // the following requests.  Elements are requested in chunks of CH per
+  // thread, all CH before any LDS write.
   constexpr int ELD = (2 * NP * PMAX + NT - 1) / NT;  // bound for n <= PMAX
   constexpr int CH = ELD < 16 ? ELD : 16;
   {
     const int tid = opaque_tid();
-    if (g.contiguous) {
-      const int64_t lend = (l0 + TL < a.nlines) ? l0 + TL : a.nlines;
-      const int valid = int((lend - l0) * n);
-      const int64_t base = l0 * n;
-      // t = f / n without an integer division: f < 2^18 and n <= 8192 keep the
-      // float quotient at least 1/(2n) away from the next integer.
-      const float inv_n = 1.0f / float(n);
-      for (int c = 0; c < ELD && c * NT < TL * n; c += CH) {
-        T ld[CH];
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-          const int f = tid + (c + i) * NT;
-          ld[i] = (f < valid) ? load_elem<T>(a.src, base + f, a.src_f64) : T(0);
-        }
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-          const int f = tid + (c + i) * NT;
-          if (f < TL * n) {
-            const int t = int((float(f) + 0.5f) * inv_n);
-            X[t * g.pitch + (f - t * n)] = ld[i];
-          }
-        }
-      }
-    } else {
+    {
       const int t = tid % TL;
       const int64_t l = l0 + t;
       const bool ok = l < a.nlines;
@@ -918,15 +893,15 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
   const cx<T>* bh = static_cast<const cx<T>*>(ax.bhat);
   const int nphase = a.kind_b >= 0 ? 2 : 1;
   const int nrep = ax.bluestein ? 2 : 1;
-  // strided tiles without a chirp convolution take the in-place shortcuts
-  const bool inplace = !g.contiguous && !ax.bluestein;
+  // without a chirp convolution the in-place shortcuts apply
+  const bool inplace = !ax.bluestein;
   bool mirrored = false;  // the middle step already built the DCT-I input
   for (int phase = 0; phase < nphase; ++phase) {
     const int kind = phase == 0 ? a.kind_f : a.kind_b;
     if (inplace && kind == K_DCT1) {
       if (!mirrored) dct1_mirror<T, NP, NT>(Z, n, ax.M);
     } else if (!(inplace && kind == K_R2HC)) {
-      pack<T, NP, NT, PMAX>(X, Z, g, kind, ax);
+      pack<T, NP, NT, PMAX>(X, Z, kind, ax);
     }
     // Stockham DFT; for Bluestein: DFT, times the kernel spectrum, conjugate, DFT
     // (the unpacker conjugates and applies the chirp).
@@ -945,7 +920,7 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
         mirrored = a.kind_b == K_DCT1;
       }
     } else {
-      unpack<T, NP, NT, PMAX>(Z, X, g, kind, ax, a, l0, scale);
+      unpack<T, NP, NT, PMAX>(Z, X, kind, ax, a, l0, scale);
     }
   }
 
@@ -955,33 +930,7 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
     const double shift = (a.update && a.shift) ? a.shift[0] : 0.0;
     double* d64 = static_cast<double*>(a.dst);
     float* d32 = static_cast<float*>(a.dst);
-    if (g.contiguous) {
-      const int64_t lend = (l0 + TL < a.nlines) ? l0 + TL : a.nlines;
-      const int valid = int((lend - l0) * n);
-      const int64_t base = l0 * n;
-      const float inv_n = 1.0f / float(n);
-      for (int c = 0; c < ELD && c * NT < valid; c += CH) {
-        double old[CH];
-        if (a.update) {
-#pragma unroll
-          for (int i = 0; i < CH; ++i) {
-            const int f = tid + (c + i) * NT;
-            old[i] = f < valid ? d64[base + f] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-          const int f = tid + (c + i) * NT;
-          if (f < valid) {
-            const int t = int((float(f) + 0.5f) * inv_n);
-            const T x = X[t * g.pitch + (f - t * n)];
-            if (a.update) d64[base + f] = old[i] + double(x) - shift;
-            else if (a.dst_f64) d64[base + f] = double(x);
-            else d32[base + f] = float(x);
-          }
-        }
-      }
-    } else {
+    {
       const int t = tid % TL;
       const int64_t l = l0 + t;
       if (l < a.nlines) {
