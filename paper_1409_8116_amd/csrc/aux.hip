@@ -4,7 +4,8 @@
 // resid_kernel computes g - m_g - L_h phi for the second-order stencil of
 // Eq. (FD2) with the boundary closure of each axis, and block partial sums of
 // w phi, w g, r^2 and (g - m_g)^2, where w is the gauge / compatibility weight
-// (1/2 on the end nodes of vertex-grid Neumann axes, 1 elsewhere).
+// (1/2 on the end nodes of vertex-grid Neumann axes, 1 elsewhere).  Without
+// phi it only forms the sums of g.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -82,6 +83,18 @@ __device__ __forceinline__ double second_diff_reg(double lo_v, double c, double 
 // independent workgroups to hide memory latency.
 constexpr int RESID_SEG = 32;
 
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8), each with its own L2.  Renumber them so that each XCD works on a
+// contiguous range of units: the axis-1 neighbour rows a unit reads are then
+// the rows of units on the same XCD, and come from its L2 instead of HBM.
+// A bijection of [0, G).
+__device__ __forceinline__ int64_t xcd_unit(int64_t b, int64_t G) {
+  constexpr int64_t kXcd = 8;
+  const int64_t q = G / kXcd, r = G % kXcd;
+  const int64_t x = b % kXcd, i = b / kXcd;
+  return x * q + (x < r ? x : r) + i;
+}
+
 __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int64_t nblk, double* part) {
   const int64_t n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
   const int64_t strips = (n2 + RESID_NT - 1) / RESID_NT;
@@ -90,7 +103,28 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
   const int64_t plane = n1 * n2;
   const double mg = a.mg ? a.mg[0] : 0.0;
   double s_wphi = 0.0, s_wg = 0.0, s_r2 = 0.0, s_g2 = 0.0;
-  for (int64_t u = blk; u < units; u += nblk) {
+  if (!a.phi) {
+    // sums of g alone (weighted mean of the right-hand side): one read of g
+    for (int64_t u = xcd_unit(blk, nblk); u < units; u += nblk) {
+      const int64_t seg = u / (strips * n1);
+      const int64_t rem = u - seg * strips * n1;
+      const int64_t i1 = rem / strips;
+      const int64_t i2 = (rem - i1 * strips) * RESID_NT + threadIdx.x;
+      if (i2 >= n2) continue;
+      const int64_t base = i1 * n2 + i2;
+      const double w12 = axis_weight(a.clo[1], i1, n1) * axis_weight(a.clo[2], i2, n2);
+      const int64_t s0 = seg * RESID_SEG;
+      const int64_t s1 = (s0 + RESID_SEG < n0) ? s0 + RESID_SEG : n0;
+#pragma unroll 4
+      for (int64_t i0 = s0; i0 < s1; ++i0) {
+        const double gv = a.g[i0 * plane + base];
+        const double gc = gv - mg;
+        s_wg += w12 * axis_weight(a.clo[0], i0, n0) * gv;
+        s_g2 += gc * gc;
+      }
+    }
+  }
+  for (int64_t u = xcd_unit(blk, nblk); a.phi && u < units; u += nblk) {
     const int64_t seg = u / (strips * n1);
     const int64_t rem = u - seg * strips * n1;
     const int64_t i1 = rem / strips;
@@ -149,7 +183,7 @@ __global__ void __launch_bounds__(RESID_NT) resid_kernel(ResidArgs a) {
 __global__ void __launch_bounds__(RESID_NT) resid_batch_kernel(BatchResidArgs b) {
   const int pi = b.blk_prob[blockIdx.x];
   ResidArgs a = b.args[pi];
-  a.phi = static_cast<const double*>(b.phi_tab[pi]);
+  a.phi = b.phi_tab ? static_cast<const double*>(b.phi_tab[pi]) : nullptr;
   a.g = static_cast<const double*>(b.g_tab[pi]);
   a.r = b.r_tab ? b.r_tab[pi] : nullptr;
   a.r_f64 = b.r_f64;

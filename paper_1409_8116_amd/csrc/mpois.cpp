@@ -782,7 +782,7 @@ hipError_t run_resid(mpois_plan_s* pl, SubPlan& sp, const void* rhs, const void*
   a.partials = static_cast<double*>(pl->partials.p);
   hipError_t e = launch_resid(a, s);
   if (e != hipSuccess) return e;
-  prof_mark(pl, 100, double(sp.npts) * (phi == rhs ? 8 : 16) + (r ? double(sp.npts) * (r_f64 ? 8 : 4) : 0), s);
+  prof_mark(pl, 100, double(sp.npts) * (phi ? 16 : 8) + (r ? double(sp.npts) * (r_f64 ? 8 : 4) : 0), s);
   e = launch_finalize(a.partials, resid_blocks(a.n), 1.0 / sp.wsum, scalars, s);
   if (e != hipSuccess) return e;
   prof_mark(pl, 101, double(resid_blocks(a.n)) * 32, s);
@@ -798,7 +798,7 @@ hipError_t enqueue_one(mpois_plan_s* pl, SubPlan& sp, size_t sub_index, const vo
   hipError_t e;
   if (sp.singular) {
     // m_g = sum w g / sum w, so the FP32 residual carries no large constant.
-    if ((e = run_resid(pl, sp, rhs, rhs, nullptr, 0, nullptr, sc, s)) != hipSuccess) return e;
+    if ((e = run_resid(pl, sp, rhs, nullptr, nullptr, 0, nullptr, sc, s)) != hipSuccess) return e;
   }
   if ((e = run_solve(pl, sp, rhs, 1, phi, 1, work, 0, false, nullptr, s)) != hipSuccess) return e;
   for (int it = 0; it < pl->max_iter; ++it) {
@@ -946,7 +946,7 @@ hipError_t enqueue_batch(mpois_plan_s* pl, hipStream_t s) {
   if (pl->prec == MPOIS_F64) return batch_solve(pl, rhs, 1, phi, 1, phi, 1, false, s);
   if (pl->prec == MPOIS_F32) return batch_solve(pl, rhs, 0, phi, 0, phi, 0, false, s);
   auto work = static_cast<void* const*>(B.work_tab.p);
-  if (B.any_singular && (e = batch_resid(pl, rhs, rhs, nullptr, false, s)) != hipSuccess) return e;
+  if (B.any_singular && (e = batch_resid(pl, nullptr, rhs, nullptr, false, s)) != hipSuccess) return e;
   if ((e = batch_solve(pl, rhs, 1, phi, 1, work, 0, false, s)) != hipSuccess) return e;
   for (int it = 0; it < pl->max_iter; ++it) {
     if ((e = batch_resid(pl, static_cast<const void* const*>(static_cast<const void*>(phi)), rhs, work, true, s)) !=
@@ -961,8 +961,8 @@ hipError_t enqueue_batch(mpois_plan_s* pl, hipStream_t s) {
 
 }  // namespace
 
-// The gauge pass above reuses run_resid with phi = rhs only to get sum w g into
-// S_WG / S_MG; the other sums of that call are not used.
+// The gauge pass above runs the residual kernel without phi: it only forms
+// sum w g (S_WG, S_MG) and sum g^2.
 
 extern "C" {
 
@@ -1114,7 +1114,8 @@ mpois_status mpois_get_info(mpois_plan pl, void* stream, mpois_info* out) {
       const void* rhs = batch ? pl->last_rhs_b[i] : pl->last_rhs;
       const void* phi = batch ? pl->last_phi_b[i] : pl->last_phi;
       double* sc = static_cast<double*>(pl->scalars.p) + i * S_COUNT;
-      if (sp.singular && run_resid(pl, sp, rhs, phi, nullptr, 0, nullptr, sc, s) != hipSuccess) return MPOIS_ERR_DEVICE;
+      if (sp.singular && run_resid(pl, sp, rhs, nullptr, nullptr, 0, nullptr, sc, s) != hipSuccess)
+        return MPOIS_ERR_DEVICE;
       if (run_resid(pl, sp, rhs, phi, nullptr, 0, sp.singular ? sc + S_MG : nullptr, sc, s) != hipSuccess)
         return MPOIS_ERR_DEVICE;
       double host[S_COUNT];
