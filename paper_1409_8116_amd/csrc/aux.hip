@@ -124,7 +124,12 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
       }
     }
   }
-  for (int64_t u = xcd_unit(blk, nblk); a.phi && u < units; u += nblk) {
+  // distinct arrays: the loads of later planes may move above the stores of r
+  const double* __restrict__ phi = a.phi;
+  const double* __restrict__ g = a.g;
+  double* __restrict__ r64 = a.r && a.r_f64 ? static_cast<double*>(a.r) : nullptr;
+  float* __restrict__ r32 = a.r && !a.r_f64 ? static_cast<float*>(a.r) : nullptr;
+  for (int64_t u = xcd_unit(blk, nblk); phi && u < units; u += nblk) {
     const int64_t seg = u / (strips * n1);
     const int64_t rem = u - seg * strips * n1;
     const int64_t i1 = rem / strips;
@@ -132,26 +137,24 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
     if (i2 >= n2) continue;
     const int64_t base = i1 * n2 + i2;
     const double w12 = axis_weight(a.clo[1], i1, n1) * axis_weight(a.clo[2], i2, n2);
-    const double first = a.phi[base];
-    const double last = a.phi[base + (n0 - 1) * plane];
+    const double first = phi[base];
+    const double last = phi[base + (n0 - 1) * plane];
     const int64_t s0 = seg * RESID_SEG;
     const int64_t s1 = (s0 + RESID_SEG < n0) ? s0 + RESID_SEG : n0;
-    double prev = s0 > 0 ? a.phi[base + (s0 - 1) * plane] : 0.0;
-    double cur = a.phi[base + s0 * plane];
-    double next = s0 + 1 < n0 ? a.phi[base + (s0 + 1) * plane] : cur;
+    double prev = s0 > 0 ? phi[base + (s0 - 1) * plane] : 0.0;
+    double cur = phi[base + s0 * plane];
+    double next = s0 + 1 < n0 ? phi[base + (s0 + 1) * plane] : cur;
 #pragma unroll 4
     for (int64_t i0 = s0; i0 < s1; ++i0) {
       const int64_t idx = i0 * plane + base;
-      const double gv = a.g[idx];
-      const double lap = a.inv_h2[2] * second_diff(a.phi, idx, i2, n2, 1, a.clo[2], cur) +
-                         a.inv_h2[1] * second_diff(a.phi, idx, i1, n1, n2, a.clo[1], cur) +
+      const double gv = g[idx];
+      const double lap = a.inv_h2[2] * second_diff(phi, idx, i2, n2, 1, a.clo[2], cur) +
+                         a.inv_h2[1] * second_diff(phi, idx, i1, n1, n2, a.clo[1], cur) +
                          a.inv_h2[0] * second_diff_reg(prev, cur, next, i0, n0, a.clo[0], last, first);
       const double gc = gv - mg;
       const double r = gc - lap;
-      if (a.r) {
-        if (a.r_f64) static_cast<double*>(a.r)[idx] = r;
-        else static_cast<float*>(a.r)[idx] = float(r);
-      }
+      if (r64) r64[idx] = r;
+      else if (r32) r32[idx] = float(r);
       const double w = w12 * axis_weight(a.clo[0], i0, n0);
       s_wphi += w * cur;
       s_wg += w * gv;
@@ -159,7 +162,7 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
       s_g2 += gc * gc;
       prev = cur;
       cur = next;
-      next = (i0 + 2 < n0) ? a.phi[idx + 2 * plane] : cur;
+      next = (i0 + 2 < n0) ? phi[idx + 2 * plane] : cur;
     }
   }
   __shared__ double red[4][RESID_NT];

@@ -490,7 +490,9 @@ int default_cfg(bool f64, int n, int P, bool rader, bool odd) {
     const bool two = kernel_cfg_slim(i) && line_pass_lds(i, n, P) <= size_t(kMaxLds / 2);
     // a Rader stage keeps many values per lane: smaller workgroups and tiles
     // leave the registers to it (measured fastest on 512^3 DCT-I passes)
-    const long score = rader ? (nt == 256 ? 100 : 0) - np : (two ? 1000 : 0) + np * 10 + (nt == 512 ? 1 : 0);
+    // ties go to the smaller work-length bound (fewer guarded unrolled steps)
+    const long score = (rader ? (nt == 256 ? 10000 : 0) - np * 100 : (two ? 10000 : 0) + np * 100 + (nt == 512 ? 10 : 0)) -
+                       pmax / 1024;
     if (score > best_score) {
       best = i;
       best_score = score;
