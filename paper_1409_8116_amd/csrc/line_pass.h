@@ -265,6 +265,7 @@ __device__ __forceinline__ void dft_any(cx<T>* v) {
   else if constexpr (R == 4) dft4(v);
   else if constexpr (R == 8) dft8(v);
   else if constexpr (R == 9) dft_2level<T, 3, 3>(v);
+  else if constexpr (R == 14) dft_2level<T, 7, 2>(v);
   else if constexpr (R == 16) dft_2level<T, 4, 4>(v);
   else if constexpr (R == 18) dft_2level<T, 2, 9>(v);
   else if constexpr (R == 36) dft_2level<T, 4, 9>(v);
@@ -522,6 +523,10 @@ __device__ __forceinline__ void dft_engine(cx<T>* Z, int P, int nstages, const S
         break;
       case 13:
         if constexpr (SLIM == 0) stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t);
+        break;
+      case 14:
+        // only after a Rader stage (1022 = 73 x 14): one LDS sweep instead of 7 and 2
+        if constexpr (RADER != 0) stage<T, 14, NP, NT, PMAX>(Z, P, st.ns, t);
         break;
       case 16: stage<T, 16, NP, NT, PMAX>(Z, P, st.ns, t); break;
       case 32:

@@ -148,6 +148,12 @@ bool factor_radices(int64_t M, bool f64, bool exact, std::vector<int>* out) {
     ++e;
   }
   if (m != 1) return false;
+  // after a Rader stage (Rader shapes carry a radix-14 codelet) a lone factor
+  // 2 joins a 7: 1022 = 73 x 14 runs in two stages
+  if (!out->empty() && out->front() == kRaderPrime && e == 1 && out->back() == 7) {
+    out->back() = 14;
+    e = 0;
+  }
   const int emax = f64 ? 4 : 5;  // radix <= 16 in FP64, <= 32 in FP32 (register budget)
   if (e > 0) {
     const int nst = (e + emax - 1) / emax;

@@ -112,8 +112,8 @@ def test_axis_plans(mp):
     assert p["P"] >= 2 * 1021 - 1 and int(np.prod(p["radices"])) == p["P"]
     p = mp.axis_plan("D", "v", 1024)  # M = 2050 = 2 * 5^2 * 41
     assert p["M"] == 2050 and p["P"] >= 4099 and set(p["radices"]) <= {2, 4, 8, 16, 3, 9, 5, 7, 11, 13}
-    p = mp.axis_plan("N", "v", 512)  # 1022 = 2 * 7 * 73: Rader stage, no convolution
-    assert p["P"] == 1022 and p["radices"][0] == 73
+    p = mp.axis_plan("N", "v", 512)  # 1022 = 73 * 14: Rader stage, then one radix-14 stage
+    assert p["P"] == 1022 and list(p["radices"]) == [73, 14]
     for n in range(1, 300):
         for bc, grid in (("P", "v"), ("N", "s"), ("D", "v"), ("N", "v")):
             if (bc, grid) == ("N", "v") and n < 2:
