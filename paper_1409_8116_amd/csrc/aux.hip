@@ -17,35 +17,45 @@ __device__ __forceinline__ double axis_weight(int clo, int64_t i, int64_t n) {
   return (clo == C_NV && (i == 0 || i == n - 1)) ? 0.5 : 1.0;
 }
 
-// Second difference along one axis at index i (stride s) with the closure of that axis.
-__device__ __forceinline__ double second_diff(const double* __restrict__ phi, int64_t idx, int64_t i,
-                                              int64_t n, int64_t s, int clo, double c) {
-  if (clo == C_NONE) return 0.0;
-  double lo, hi;
-  if (i > 0) lo = phi[idx - s];
-  else {
-    switch (clo) {
-      case C_PER: lo = phi[idx + (n - 1) * s]; break;
-      case C_DV: lo = 0.0; break;
-      case C_DS: lo = -c; break;
-      case C_NV: lo = phi[idx + s]; break;
-      default: lo = c; break;  // C_NS
-    }
-  }
-  if (i < n - 1) hi = phi[idx + s];
-  else {
-    switch (clo) {
-      case C_PER: hi = phi[idx - (n - 1) * s]; break;
-      case C_DV: hi = 0.0; break;
-      case C_DS: hi = -c; break;
-      case C_NV: hi = phi[idx - s]; break;
-      default: hi = c; break;
-    }
-  }
-  return lo - 2.0 * c + hi;
-}
-
 constexpr int RESID_NT = 256;
+
+// The two neighbours of a point along one axis, for a fixed index i on that
+// axis: neighbour = a * phi[idx + d] + b * phi[idx], which covers the
+// interior (a = 1) and every closure of the boundary nodes (wrap-around or
+// mirror offsets, Dirichlet zero a = b = 0, staggered Dirichlet b = -1,
+// staggered Neumann b = 1; an axis without closure gives a zero difference).
+struct Neighbours {
+  int64_t dlo, dhi;
+  double alo, ahi, blo, bhi;
+};
+
+__device__ __forceinline__ Neighbours neighbours(int64_t i, int64_t n, int64_t s, int clo) {
+  Neighbours q{0, 0, 0.0, 0.0, 1.0, 1.0};
+  if (clo == C_NONE) return q;
+  if (i > 0) {
+    q.dlo = -s; q.alo = 1.0; q.blo = 0.0;
+  } else {
+    switch (clo) {
+      case C_PER: q.dlo = (n - 1) * s; q.alo = 1.0; q.blo = 0.0; break;
+      case C_DV: q.blo = 0.0; break;
+      case C_DS: q.blo = -1.0; break;
+      case C_NV: q.dlo = s; q.alo = 1.0; q.blo = 0.0; break;
+      default: break;  // C_NS: phi itself
+    }
+  }
+  if (i < n - 1) {
+    q.dhi = s; q.ahi = 1.0; q.bhi = 0.0;
+  } else {
+    switch (clo) {
+      case C_PER: q.dhi = -(n - 1) * s; q.ahi = 1.0; q.bhi = 0.0; break;
+      case C_DV: q.bhi = 0.0; break;
+      case C_DS: q.bhi = -1.0; break;
+      case C_NV: q.dhi = -s; q.ahi = 1.0; q.bhi = 0.0; break;
+      default: break;
+    }
+  }
+  return q;
+}
 
 // Second difference along axis 0 from values held in registers.
 __device__ __forceinline__ double second_diff_reg(double lo_v, double c, double hi_v, int64_t i, int64_t n, int clo,
@@ -137,24 +147,30 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
     if (i2 >= n2) continue;
     const int64_t base = i1 * n2 + i2;
     const double w12 = axis_weight(a.clo[1], i1, n1) * axis_weight(a.clo[2], i2, n2);
-    const double first = phi[base];
-    const double last = phi[base + (n0 - 1) * plane];
+    // axes 2 and 1: neighbour offsets and weights are fixed for this thread
+    const Neighbours q2 = neighbours(i2, n2, 1, a.clo[2]);
+    const Neighbours q1 = neighbours(i1, n1, n2, a.clo[1]);
+    const double* __restrict__ pp = phi + base;
+    const double* __restrict__ gp = g + base;
+    const double first = pp[0];
+    const double last = pp[(n0 - 1) * plane];
     const int64_t s0 = seg * RESID_SEG;
     const int64_t s1 = (s0 + RESID_SEG < n0) ? s0 + RESID_SEG : n0;
-    double prev = s0 > 0 ? phi[base + (s0 - 1) * plane] : 0.0;
-    double cur = phi[base + s0 * plane];
-    double next = s0 + 1 < n0 ? phi[base + (s0 + 1) * plane] : cur;
+    double prev = s0 > 0 ? pp[(s0 - 1) * plane] : 0.0;
+    double cur = pp[s0 * plane];
+    double next = s0 + 1 < n0 ? pp[(s0 + 1) * plane] : cur;
+    int64_t o = s0 * plane;
 #pragma unroll 4
-    for (int64_t i0 = s0; i0 < s1; ++i0) {
-      const int64_t idx = i0 * plane + base;
-      const double gv = g[idx];
-      const double lap = a.inv_h2[2] * second_diff(phi, idx, i2, n2, 1, a.clo[2], cur) +
-                         a.inv_h2[1] * second_diff(phi, idx, i1, n1, n2, a.clo[1], cur) +
+    for (int64_t i0 = s0; i0 < s1; ++i0, o += plane) {
+      const double gv = gp[o];
+      const double d2 = q2.alo * pp[o + q2.dlo] + q2.blo * cur - 2.0 * cur + q2.ahi * pp[o + q2.dhi] + q2.bhi * cur;
+      const double d1 = q1.alo * pp[o + q1.dlo] + q1.blo * cur - 2.0 * cur + q1.ahi * pp[o + q1.dhi] + q1.bhi * cur;
+      const double lap = a.inv_h2[2] * d2 + a.inv_h2[1] * d1 +
                          a.inv_h2[0] * second_diff_reg(prev, cur, next, i0, n0, a.clo[0], last, first);
       const double gc = gv - mg;
       const double r = gc - lap;
-      if (r64) r64[idx] = r;
-      else if (r32) r32[idx] = float(r);
+      if (r64) r64[base + o] = r;
+      else if (r32) r32[base + o] = float(r);
       const double w = w12 * axis_weight(a.clo[0], i0, n0);
       s_wphi += w * cur;
       s_wg += w * gv;
@@ -162,7 +178,7 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
       s_g2 += gc * gc;
       prev = cur;
       cur = next;
-      next = (i0 + 2 < n0) ? phi[idx + 2 * plane] : cur;
+      next = (i0 + 2 < n0) ? pp[o + 2 * plane] : cur;
     }
   }
   __shared__ double red[4][RESID_NT];
