@@ -452,24 +452,18 @@ __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P, int ns, const cx<
     dft_any<T, K>(x);
 #pragma unroll
     for (int k1 = 1; k1 < K; ++k1) x[k1] = cmul(x[k1], w72[s * k1]);
-#pragma unroll
-    for (int h = G / 2; h >= 1; h >>= 1) {
-      if (h == 4) lane_radix2<T, K, 4, false>(x, s);
-      if (h == 2) lane_radix2<T, K, 2, false>(x, s);
-      if (h == 1) lane_radix2<T, K, 1, false>(x, s);
-    }
+    if constexpr (G >= 8) lane_radix2<T, K, 4, false>(x, s);
+    if constexpr (G >= 4) lane_radix2<T, K, 2, false>(x, s);
+    lane_radix2<T, K, 1, false>(x, s);
     // lane s holds A[k1 + K bitrev(s)]; X[0] = v0 + A[0] (lane 0, k1 = 0)
     const int k2 = lane_bitrev<G>(s);
     out0[i] = v0 + x[0];
 #pragma unroll
     for (int k1 = 0; k1 < K; ++k1) x[k1] = conj(cmul(x[k1], dhat[k1 + K * k2]));
     // second length-72 DFT: across lanes first (bit-reversed in, natural out)
-#pragma unroll
-    for (int h = 1; h <= G / 2; h <<= 1) {
-      if (h == 1) lane_radix2<T, K, 1, true>(x, s);
-      if (h == 2) lane_radix2<T, K, 2, true>(x, s);
-      if (h == 4) lane_radix2<T, K, 4, true>(x, s);
-    }
+    lane_radix2<T, K, 1, true>(x, s);
+    if constexpr (G >= 4) lane_radix2<T, K, 2, true>(x, s);
+    if constexpr (G >= 8) lane_radix2<T, K, 4, true>(x, s);
 #pragma unroll
     for (int j2 = 1; j2 < K; ++j2) x[j2] = cmul(x[j2], w72[j2 * s]);
     dft_any<T, K>(x);
