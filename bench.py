@@ -15,6 +15,7 @@ Other workloads (one JSON line each, same keys):
   mixed256    256^3 staggered P/D/N box, FP64 and FP32, FD and pseudo-spectral
   batch2048   2048 independent 2D grids (sides 64..1024), FP32 + refinement, one batched launch set
   channel     1024x512x256 channel, graph-captured FP32 + refinement, stream of RHS
+  copy        plain 1 GiB device-to-device copy (calibrates the HBM byte counters)
 
 Prints one JSON line per workload on stdout; progress goes to stderr.
 """
@@ -155,7 +156,7 @@ def run_neumann(args):
     rhs = torch.tensor(g, dtype=torch.float64, device="cuda")
     phi_r = torch.empty_like(rhs)
     phi_64 = torch.empty_like(rhs)
-    plan_r = mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter)
+    plan_r = mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, f64_arith=args.f64_arith)
     plan_64 = mp.Plan.from_desc(d, prec="f64")
     log("timing FP32 + refinement")
     ms_r, wall_r = timed(lambda: plan_r.solve(rhs, phi_r), args.steps, args.warmup)
@@ -165,7 +166,8 @@ def run_neumann(args):
     ms_64, _ = timed(lambda: plan_64.solve(rhs, phi_64), args.steps, args.warmup)
     info_64 = plan_64.info()
     log(f"  {ms_64:.3f} ms/solve, rel resid {info_64['rel_resid']:.3e}")
-    roof = profile_plan(lambda: mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, profile=True), rhs)
+    roof = profile_plan(lambda: mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, profile=True,
+                                                  f64_arith=args.f64_arith), rhs)
     roof64 = profile_plan(lambda: mp.Plan.from_desc(d, prec="f64", profile=True), rhs)
     log(f"dominant kernel (f32r) {roof['kernel']}: {roof['avg_launch_ms']:.3f} ms avg, {roof['achieved']:.0f} GB/s")
     log(f"dominant kernel (f64) {roof64['kernel']}: {roof64['avg_launch_ms']:.3f} ms avg, {roof64['achieved']:.0f} GB/s")
@@ -315,7 +317,20 @@ def run_channel(args):
     return [out]
 
 
-WORKLOADS = {"neumann512": run_neumann, "periodic32": run_periodic32, "mixed256": run_mixed256,
+def run_copy(args):
+    """A device copy of known size: the FETCH_SIZE / WRITE_SIZE counters it reads,
+    divided by its bytes, scale the counters of the solver kernels."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    ms, _ = timed(lambda: dst.copy_(src), max(args.steps, 3), 1)
+    out = base_record(args, "device copy GB/s", 2 * nbytes / (ms * 1e-3) / 1e9, "GB/s", ms, "f64",
+                      {"workload": "copy_1GiB"})
+    return [out]
+
+
+WORKLOADS = {"copy": run_copy, "neumann512": run_neumann, "periodic32": run_periodic32, "mixed256": run_mixed256,
              "batch2048": run_batch, "channel": run_channel}
 
 
@@ -329,6 +344,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=2)
     ap.add_argument("--nrhs", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--f64-arith", action="store_true",
+                    help="refinement plans compute the transforms in FP64 on FP32-stored data")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this solver build has no multi-GPU path "

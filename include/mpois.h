@@ -60,6 +60,10 @@ typedef enum { MPOIS_F64 = 0, MPOIS_F32 = 1, MPOIS_F32_REFINE = 2 } mpois_prec;
 #define MPOIS_FLAG_GRAPH 1u   /* capture the launch sequence once per (rhs, phi) pair and replay it */
 #define MPOIS_FLAG_TUNE 2u    /* time the candidate kernel shapes at plan creation and keep the fastest */
 #define MPOIS_FLAG_PROFILE 4u /* record an event after every launch of an execute (not captured) */
+#define MPOIS_FLAG_F64_ARITH 8u /* MPOIS_F32_REFINE only: the transforms compute in FP64 on data that stays
+                                   FP32 in memory (working array, residual); each stored value is then
+                                   rounded relative to its own size, so a correction contracts the error
+                                   by about the FP32 unit roundoff */
 
 /* One grid.  ndim in 1..3; n[d] >= 1 (>= 2 on vertex Neumann axes); h[d] > 0
  * finite; bc[d][0] and bc[d][1] are the two faces of axis d and must be equal

@@ -28,6 +28,7 @@ PREC = {"f64": 0, "f32": 1, "f32r": 2}
 FLAG_GRAPH = 1
 FLAG_TUNE = 2
 FLAG_PROFILE = 4
+FLAG_F64_ARITH = 8
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory", 4: "device error",
           5: "refinement did not reach rtol", 6: "non-finite residual"}
 KIND_NAMES = ["R2HC", "HC2R", "DCT-II", "DCT-III", "DST-II", "DST-III", "DCT-I", "DST-I"]
@@ -171,11 +172,12 @@ class Plan:
     """One grid: mpois_plan_create / mpois_execute / mpois_destroy."""
 
     def __init__(self, shape, h, bc, grid, approx="fd", prec="f64", rtol=0.0, max_iter=2, graph=False, tune=False,
-                 profile=False):
+                 profile=False, f64_arith=False):
         self.lib = load_library()
         self.shape = tuple(int(n) for n in shape)
         self.prec = prec
-        flags = (FLAG_GRAPH if graph else 0) | (FLAG_TUNE if tune else 0) | (FLAG_PROFILE if profile else 0)
+        flags = (FLAG_GRAPH if graph else 0) | (FLAG_TUNE if tune else 0) | (FLAG_PROFILE if profile else 0) | \
+            (FLAG_F64_ARITH if f64_arith else 0)
         self._desc = make_desc(shape, h, bc, grid)
         handle = ctypes.c_void_p()
         st = self.lib.mpois_plan_create(ctypes.byref(self._desc), APPROX[approx], PREC[prec], float(rtol),
@@ -244,7 +246,8 @@ class Plan:
 class BatchPlan:
     """Many independent grids of one ndim: mpois_plan_create_batch / mpois_execute_batch."""
 
-    def __init__(self, descs, prec="f64", approx=None, rtol=0.0, max_iter=2, graph=False, tune=False):
+    def __init__(self, descs, prec="f64", approx=None, rtol=0.0, max_iter=2, graph=False, tune=False,
+                 f64_arith=False):
         self.lib = load_library()
         self.descs = list(descs)
         self.prec = prec
@@ -253,7 +256,7 @@ class BatchPlan:
         for i, d in enumerate(self.descs):
             arr[i] = make_desc(d["shape"], d["h"], d["bc"], d["grid"])
         self._arr = arr
-        flags = (FLAG_GRAPH if graph else 0) | (FLAG_TUNE if tune else 0)
+        flags = (FLAG_GRAPH if graph else 0) | (FLAG_TUNE if tune else 0) | (FLAG_F64_ARITH if f64_arith else 0)
         handle = ctypes.c_void_p()
         st = self.lib.mpois_plan_create_batch(arr, len(self.descs), APPROX[approx], PREC[prec], float(rtol),
                                               int(max_iter), flags, ctypes.byref(handle))

@@ -1,7 +1,10 @@
 """Build libmpois.so (HIP kernels + C ABI) in-tree for gfx950 with hipcc."""
+import glob
+import hashlib
 import os
 import subprocess
 import sys
+import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -16,29 +19,50 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
-def build(verbose=False, jobs=None):
+def _inputs():
+    return sorted(glob.glob(os.path.join(CSRC, "*")) + [os.path.join(ROOT, "include", "mpois.h")])
+
+
+def build_id():
+    """Hash of every source the library is built from (keys the tuner cache)."""
+    h = hashlib.sha256()
+    for f in _inputs():
+        if os.path.isfile(f):
+            with open(f, "rb") as fh:
+                h.update(os.path.basename(f).encode() + fh.read())
+    return h.hexdigest()[:12]
+
+
+def build(verbose=False, jobs=None, incremental=False):
+    """Compile every object and link libmpois.so.  incremental=True skips
+    objects newer than every source (a developer convenience; the default
+    rebuilds everything)."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     jobs = jobs or max(1, min(16, os.cpu_count() or 1))
+    newest = max(os.path.getmtime(f) for f in _inputs() if os.path.isfile(f))
+    bid = ["-DMPOIS_BUILD_ID=\"" + build_id() + "\""]
     cmds, objs = [], []
     for i in range(NUM_SHAPES):
         obj = os.path.join(objdir, f"lp_inst_{i}.o")
-        cmds.append([HIPCC] + FLAGS + [f"-DMPOIS_CFG={i}", "-c", os.path.join(CSRC, "lp_inst.hip"), "-o", obj])
         objs.append(obj)
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > newest:
+            continue
+        cmds.append([HIPCC] + FLAGS + [f"-DMPOIS_CFG={i}", "-c", os.path.join(CSRC, "lp_inst.hip"), "-o", obj])
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmds.append([HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+        if incremental and src != "tune.cpp" and os.path.exists(obj) and os.path.getmtime(obj) > newest:
+            continue
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        cmds.append([HIPCC] + FLAGS + bid + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
     running = []
     for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        running.append(subprocess.Popen(cmd))
-        while len([p for p in running if p.poll() is None]) >= jobs:
-            running[0].wait() if running[0].poll() is None else None
-            import time
+        while sum(p.poll() is None for p in running) >= jobs:
             time.sleep(0.2)
+        running.append(subprocess.Popen(cmd))
     for p in running:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
@@ -52,5 +76,5 @@ def build(verbose=False, jobs=None):
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
     print("built", LIB)

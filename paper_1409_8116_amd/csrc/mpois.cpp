@@ -123,7 +123,7 @@ void axis_eigs(int bc, int grid, int approx, int64_t n, double h, double* out) {
 // as even radices as the register budget allows (at most 16 in FP64, 32 in
 // FP32).  Returns false if a prime the codelets do not cover remains.
 constexpr int kRaderPrime = 73;
-bool factor_radices(int64_t M, bool f64, bool exact, std::vector<int>* out) {
+bool factor_radices(int64_t M, bool f64, bool exact, std::vector<int>* out, int extra_pow2_stages = 0) {
   out->clear();
   int64_t m = M;
   if (exact && M <= 1024 && m % kRaderPrime == 0) {
@@ -156,7 +156,8 @@ bool factor_radices(int64_t M, bool f64, bool exact, std::vector<int>* out) {
   }
   const int emax = f64 ? 4 : 5;  // radix <= 16 in FP64, <= 32 in FP32 (register budget)
   if (e > 0) {
-    const int nst = (e + emax - 1) / emax;
+    int nst = (e + emax - 1) / emax + extra_pow2_stages;
+    if (nst > e) nst = e;
     for (int i = 0; i < nst; ++i) {
       const int ei = e / nst + (i < e % nst ? 1 : 0);
       out->push_back(1 << ei);
@@ -216,6 +217,41 @@ AxisShape plan_axis_shape(int bc, int grid, int64_t n, bool f64) {
   return s;
 }
 
+// Candidate radix plans of one axis for the autotuner, the default first:
+// the stage order reversed, the power-of-two part split into one more stage,
+// and a Bluestein convolution in place of an exact plan that needs the Rader
+// stage or a radix-11/13 codelet.  Deterministic for given arguments (the
+// tuner cache stores an index into this list).
+std::vector<AxisShape> axis_variants(int bc, int grid, int64_t n, bool f64) {
+  std::vector<AxisShape> v;
+  const AxisShape d = plan_axis_shape(bc, grid, n, f64);
+  v.push_back(d);
+  auto add = [&](const AxisShape& s) {
+    for (const AxisShape& o : v)
+      if (o.bluestein == s.bluestein && o.P == s.P && o.radices == s.radices) return;
+    v.push_back(s);
+  };
+  if (d.radices.size() >= 2) {
+    AxisShape r = d;
+    std::reverse(r.radices.begin(), r.radices.end());
+    add(r);
+  }
+  {
+    AxisShape x = d;
+    if (factor_radices(d.P, f64, !d.bluestein, &x.radices, 1)) add(x);
+  }
+  bool big_odd = false;
+  for (int r : d.radices) big_odd = big_odd || r == kRaderPrime || r == 11 || r == 13;
+  if (!d.bluestein && big_odd && d.M > 1) {
+    AxisShape b = d;
+    b.bluestein = true;
+    b.P = 2 * d.M - 1;
+    while (!factor_radices(b.P, f64, false, &b.radices)) ++b.P;
+    add(b);
+  }
+  return v;
+}
+
 bool has_rader(const AxisShape& s) {
   for (int r : s.radices)
     if (r == kRaderPrime) return true;
@@ -233,6 +269,7 @@ bool has_odd_large(const AxisShape& s) {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool pooled = false;  // carved from the plan's table pool (freed with the pool)
 };
 
 struct AxisTables {
@@ -266,7 +303,6 @@ struct SubPlan {
   double h[3] = {1, 1, 1};
   bool singular = false;
   double wsum = 0;              // sum of gauge weights
-  std::vector<int> axis_table;  // index into Plan::tables per (real) axis
   std::vector<DevBuf> lam;      // scaled eigenvalues per axis (working precision)
   std::vector<Pass> passes;     // forward ... fused ... inverse
   ResidArgs resid{};
@@ -299,8 +335,12 @@ struct BatchState {
   DevBuf resid_args, blk_prob, blk_start, blk_count, inv_wsum, partials;
   int resid_blocks = 0;
   bool any_singular = false;
-  std::vector<const void*> host_rhs;
-  std::vector<void*> host_phi;
+  // Pointer tables as last validated and uploaded: pinned host staging
+  // (rhs pointers, then phi pointers), and an event that marks the end of the
+  // upload so the staging is not rewritten while a copy from it is pending.
+  void** staging = nullptr;
+  hipEvent_t uploaded = nullptr;
+  bool have_tables = false;
 };
 
 struct Graph {
@@ -319,7 +359,7 @@ struct mpois_plan_s {
   int device = 0;
   bool f64work = true;
   std::vector<AxisTables> tables;
-  std::map<std::pair<int, int64_t>, int> table_index;  // (kind_f, n) -> tables index... keyed with bc/grid
+  std::map<std::string, int> table_index;  // shape_key -> index into tables
   std::vector<SubPlan> subs;
   DevBuf work;       // FP32 working array (refinement)
   DevBuf partials;   // resid partials
@@ -327,6 +367,8 @@ struct mpois_plan_s {
   size_t bytes = 0;
   const void* last_rhs = nullptr;
   void* last_phi = nullptr;
+  const void* checked_rhs = nullptr;  // last pointer pair that passed check_ptrs
+  void* checked_phi = nullptr;
   std::vector<const void*> last_rhs_b;
   std::vector<void*> last_phi_b;
   int last_iters = 0;
@@ -338,6 +380,9 @@ struct mpois_plan_s {
   std::vector<ProfRec> prof;
   size_t prof_used = 0;
   bool profiling = false;
+  TuneSession* tune = nullptr;  // measurement scratch while the plan is built
+  std::vector<void*> pool;      // chunks holding the small device buffers
+  size_t pool_used = 0;         // bytes used in the last chunk
 };
 
 namespace {
@@ -347,9 +392,33 @@ bool fault_alloc() {
   return e && e[0] == '1';
 }
 
+// Small buffers (tables, descriptions) are carved from pool chunks of
+// kPoolChunk bytes, so a plan with thousands of axis tables makes few
+// device allocations.
+constexpr size_t kPoolChunk = size_t(8) << 20;
+constexpr size_t kPoolMax = size_t(1) << 20;
+
 mpois_status dev_alloc(mpois_plan_s* pl, DevBuf* b, size_t bytes) {
   if (bytes == 0) return MPOIS_OK;
   if (fault_alloc()) return MPOIS_ERR_NOMEM;
+  if (bytes <= kPoolMax) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (pl->pool.empty() || pl->pool_used + need > kPoolChunk) {
+      void* c = nullptr;
+      if (hipMalloc(&c, kPoolChunk) != hipSuccess) {
+        (void)hipGetLastError();
+        return MPOIS_ERR_NOMEM;
+      }
+      pl->pool.push_back(c);
+      pl->pool_used = 0;
+      pl->bytes += kPoolChunk;
+    }
+    b->p = static_cast<char*>(pl->pool.back()) + pl->pool_used;
+    b->bytes = bytes;
+    b->pooled = true;
+    pl->pool_used += need;
+    return MPOIS_OK;
+  }
   if (hipMalloc(&b->p, bytes) != hipSuccess) {
     b->p = nullptr;
     (void)hipGetLastError();
@@ -370,7 +439,7 @@ mpois_status dev_upload(mpois_plan_s* pl, DevBuf* b, const std::vector<V>& host)
 }
 
 void dev_free(DevBuf* b) {
-  if (b->p) (void)hipFree(b->p);
+  if (b->p && !b->pooled) (void)hipFree(b->p);
   b->p = nullptr;
   b->bytes = 0;
 }
@@ -567,19 +636,89 @@ mpois_status upload_lam(mpois_plan_s* pl, DevBuf* b, const std::vector<double>& 
   return dev_upload(pl, b, h);
 }
 
-int table_for(mpois_plan_s* pl, int bc, int grid, int64_t n, mpois_status* st) {
-  const int key_kind = bc * 2 + (bc == MPOIS_PERIODIC ? 0 : grid);
-  auto key = std::make_pair(key_kind, n);
+std::string shape_key(int bc, int grid, int64_t n, const AxisShape& sh) {
+  std::string k = std::to_string(bc * 2 + (bc == MPOIS_PERIODIC ? 0 : grid)) + "/" + std::to_string(n) + "/" +
+                  std::to_string(sh.P) + (sh.bluestein ? "b" : "e");
+  for (int r : sh.radices) k += "." + std::to_string(r);
+  return k;
+}
+
+// Device tables of one axis transform with radix plan `shape`, shared by
+// every pass of the plan that uses the same one.
+int table_for(mpois_plan_s* pl, int bc, int grid, int64_t n, const AxisShape& shape, mpois_status* st) {
+  const std::string key = shape_key(bc, grid, n, shape);
   auto it = pl->table_index.find(key);
   if (it != pl->table_index.end()) return it->second;
   AxisTables at;
-  at.shape = plan_axis_shape(bc, grid, n, pl->f64work);
+  at.shape = shape;
   at.n = n;
   pl->tables.push_back(at);
   const int idx = int(pl->tables.size()) - 1;
   *st = pl->f64work ? build_axis_tables<double>(pl, &pl->tables[idx]) : build_axis_tables<float>(pl, &pl->tables[idx]);
   pl->table_index[key] = idx;
   return idx;
+}
+
+// Measured choice of radix plan and kernel shape for one pass (MPOIS_FLAG_TUNE).
+// Candidates: every radix plan of axis_variants times every kernel shape that
+// holds it; each is timed on scratch arrays with the pass's line count (for
+// batch plans a fixed count of at least 2048 lines: their passes share the
+// chip with the other grids', so throughput per line is what counts).  The
+// decision is cached under a key of precision, kinds, axis kind, length,
+// stride class and line count.  Returns the index of the chosen plan's
+// tables (and the shape in *cfg), or -1 if nothing could be measured.
+int tune_axis_pass(mpois_plan_s* pl, const PassArgs& proto, int bc, int grid, int64_t n, int* cfg,
+                   mpois_status* st) {
+  const bool f64 = pl->f64work;
+  const std::vector<AxisShape> vars = axis_variants(bc, grid, n, f64);
+  int64_t lines = proto.nlines;
+  if (pl->subs.size() > 1) {
+    lines = std::max<int64_t>(lines, 2048);
+    lines = (lines + proto.inner - 1) / proto.inner * proto.inner;
+  }
+  const std::string key = std::string(f64 ? "f64" : "f32") + "/kf" + std::to_string(proto.kind_f) + "/kb" +
+                          std::to_string(proto.kind_b) + "/bc" + std::to_string(bc) + std::to_string(grid) + "/n" +
+                          std::to_string(n) + (proto.inner == 1 ? "/c" : "/s") +
+                          (pl->subs.size() > 1 ? std::string("/tput") : "/l" + std::to_string(lines));
+  // MPOIS_TUNE_VARIANT=k restricts the candidates to radix plan k of
+  // axis_variants (when it exists), bypassing the cache: a test hook that
+  // makes every plan variant reachable.
+  const char* force = std::getenv("MPOIS_TUNE_VARIANT");
+  const int only = force ? std::atoi(force) : -1;
+  int vi = -1, ci = -1;
+  if (only < 0 && tune_lookup(key, &vi, &ci) && vi >= 0 && vi < int(vars.size()) &&
+      cfg_fits(ci, f64, int(n), int(vars[vi].P), has_rader(vars[vi]), has_odd_large(vars[vi]))) {
+    *cfg = ci;
+    return table_for(pl, bc, grid, n, vars[vi], st);
+  }
+  if (!pl->tune) pl->tune = tune_begin();
+  double best = 1e300;
+  int best_t = -1;
+  vi = ci = -1;
+  for (size_t v = 0; v < vars.size(); ++v) {
+    if (only >= 0 && only < int(vars.size()) && int(v) != only) continue;
+    const AxisShape& sh = vars[v];
+    const int t = table_for(pl, bc, grid, n, sh, st);
+    if (*st != MPOIS_OK) return -1;
+    PassArgs a = proto;
+    a.ax = pl->tables[t].dev;
+    for (int c = 0; c < num_kernel_cfgs(); ++c) {
+      if (!cfg_fits(c, f64, int(n), int(sh.P), has_rader(sh), has_odd_large(sh))) continue;
+      const double ms = tune_time(pl->tune, a, c, lines);
+      if (std::getenv("MPOIS_LOG"))
+        std::fprintf(stderr, "[mpois tune] %s plan %zu shape %d: %.4f ms\n", key.c_str(), v, c, ms);
+      if (ms >= 0 && ms < best) {
+        best = ms;
+        best_t = t;
+        vi = int(v);
+        ci = c;
+      }
+    }
+  }
+  if (best_t < 0) return -1;
+  if (only < 0) tune_store(key, vi, ci);
+  *cfg = ci;
+  return best_t;
 }
 
 mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) {
@@ -608,11 +747,8 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
   double c = 1.0;
   for (int d = 0; d < D; ++d) c *= axis_norm(g->bc[d][0], g->grid[d], g->n[d]);
   mpois_status st = MPOIS_OK;
-  sp->axis_table.resize(D);
   sp->lam.resize(D);
   for (int d = 0; d < D; ++d) {
-    sp->axis_table[d] = table_for(pl, g->bc[d][0], g->grid[d], g->n[d], &st);
-    if (st != MPOIS_OK) return st;
     std::vector<double> lam(static_cast<size_t>(g->n[d]));
     axis_eigs(g->bc[d][0], g->grid[d], pl->approx, g->n[d], g->h[d], lam.data());
     for (auto& v : lam) v /= c;
@@ -622,17 +758,18 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
   // passes (input and output pointers are filled at execute time)
   auto axis_pass = [&](int d, bool fused, bool inverse) {
     Pass p;
-    const AxisTables& at = pl->tables[sp->axis_table[d]];
+    const int bc = g->bc[d][0], grd = g->grid[d];
+    const int64_t n = g->n[d];
+    const AxisShape shape = plan_axis_shape(bc, grd, n, pl->f64work);
     PassArgs& a = p.args;
-    a.ax = at.dev;
     int64_t inner = 1;
     for (int e = d + 1; e < D; ++e) inner *= g->n[e];
     a.nlines = 1;
     for (int e = 0; e < D; ++e)
       if (e != d) a.nlines *= g->n[e];
     a.inner = inner;
-    a.kind_f = inverse ? at.shape.kind_b : at.shape.kind_f;
-    a.kind_b = fused ? at.shape.kind_b : -1;
+    a.kind_f = inverse ? shape.kind_b : shape.kind_f;
+    a.kind_b = fused ? shape.kind_b : -1;
     a.singular = sp->singular ? 1 : 0;
     if (fused) {
       a.lam_this = sp->lam[d].p;
@@ -643,14 +780,23 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
       }
     }
     p.axis = d;
-    const bool rader = has_rader(at.shape), odd = has_odd_large(at.shape);
-    p.cfg = default_cfg(pl->f64work, int(g->n[d]), int(at.shape.P), rader, odd);
-    if (tune_enabled(pl->flags) && p.cfg >= 0) p.cfg = tune_pass(a, p.cfg, pl->f64work, rader, odd);
+    int ti = -1;
+    if (tune_enabled(pl->flags)) {
+      ti = tune_axis_pass(pl, a, bc, grd, n, &p.cfg, &st);
+      if (st != MPOIS_OK) return p;
+    }
+    if (ti < 0) {
+      ti = table_for(pl, bc, grd, n, shape, &st);
+      if (st != MPOIS_OK) return p;
+      p.cfg = default_cfg(pl->f64work, int(n), int(shape.P), has_rader(shape), has_odd_large(shape));
+    }
+    a.ax = pl->tables[ti].dev;
     return p;
   };
-  for (int d = D - 1; d >= 1; --d) sp->passes.push_back(axis_pass(d, false, false));
-  sp->passes.push_back(axis_pass(0, true, false));
-  for (int d = 1; d < D; ++d) sp->passes.push_back(axis_pass(d, false, true));
+  for (int d = D - 1; d >= 1 && st == MPOIS_OK; --d) sp->passes.push_back(axis_pass(d, false, false));
+  if (st == MPOIS_OK) sp->passes.push_back(axis_pass(0, true, false));
+  for (int d = 1; d < D && st == MPOIS_OK; ++d) sp->passes.push_back(axis_pass(d, false, true));
+  if (st != MPOIS_OK) return st;
   for (const Pass& p : sp->passes)
     if (p.cfg < 0) return MPOIS_ERR_UNSUPPORTED;
   // residual description
@@ -682,6 +828,8 @@ void free_plan(mpois_plan_s* pl) {
       dev_free(&g.tile_idx);
     }
   }
+  if (pl->batch.staging) (void)hipHostFree(pl->batch.staging);
+  if (pl->batch.uploaded) (void)hipEventDestroy(pl->batch.uploaded);
   for (DevBuf* b : {&pl->batch.rhs_tab, &pl->batch.phi_tab, &pl->batch.work_tab, &pl->batch.resid_args,
                     &pl->batch.blk_prob, &pl->batch.blk_start, &pl->batch.blk_count, &pl->batch.inv_wsum,
                     &pl->batch.partials})
@@ -694,6 +842,8 @@ void free_plan(mpois_plan_s* pl) {
   if (pl->graph.exec) (void)hipGraphExecDestroy(pl->graph.exec);
   if (pl->graph.graph) (void)hipGraphDestroy(pl->graph.graph);
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  tune_end(pl->tune);
+  for (void* c : pl->pool) (void)hipFree(c);
   delete pl;
 }
 
@@ -720,12 +870,14 @@ mpois_status create_common(const mpois_grid_desc* gs, int count, int approx, int
   pl->max_iter = prec == MPOIS_F32_REFINE ? max_iter : 0;
   pl->flags = flags;
   pl->device = dev;
-  pl->f64work = prec == MPOIS_F64;
+  pl->f64work = prec == MPOIS_F64 || (prec == MPOIS_F32_REFINE && (flags & MPOIS_FLAG_F64_ARITH));
   pl->subs.resize(size_t(count));
   for (int i = 0; i < count && st == MPOIS_OK; ++i) {
     st = build_sub(pl, &gs[i], &pl->subs[i]);
     maxpts = std::max(maxpts, pl->subs[i].npts);
   }
+  tune_end(pl->tune);
+  pl->tune = nullptr;
   int64_t total_pts = 0;
   for (auto& sp : pl->subs) total_pts += sp.npts;
   const int64_t work_pts = count > 1 ? total_pts : maxpts;
@@ -882,6 +1034,13 @@ mpois_status build_batch(mpois_plan_s* pl) {
   if (st == MPOIS_OK) st = dev_alloc(pl, &B.rhs_tab, size_t(count) * sizeof(void*));
   if (st == MPOIS_OK) st = dev_alloc(pl, &B.phi_tab, size_t(count) * sizeof(void*));
   if (st != MPOIS_OK) return st;
+  if (fault_alloc() || hipHostMalloc(reinterpret_cast<void**>(&B.staging), 2 * size_t(count) * sizeof(void*),
+                                     hipHostMallocDefault) != hipSuccess) {
+    B.staging = nullptr;
+    (void)hipGetLastError();
+    return MPOIS_ERR_NOMEM;
+  }
+  if (hipEventCreateWithFlags(&B.uploaded, hipEventDisableTiming) != hipSuccess) return MPOIS_ERR_DEVICE;
   if (pl->prec == MPOIS_F32_REFINE) {
     std::vector<void*> work(static_cast<size_t>(count));
     int64_t off = 0;
@@ -942,13 +1101,12 @@ hipError_t batch_resid(mpois_plan_s* pl, const void* const* phi, const void* con
                                b.scalars, int(pl->subs.size()), s);
 }
 
+// The kernels of one batched execute; they read the array pointers from the
+// device tables, so the same sequence (or its captured graph) serves any
+// pointers once the tables hold them.
 hipError_t enqueue_batch(mpois_plan_s* pl, hipStream_t s) {
   BatchState& B = pl->batch;
-  const size_t count = pl->subs.size();
-  hipError_t e = hipMemcpyAsync(B.rhs_tab.p, B.host_rhs.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(B.phi_tab.p, B.host_phi.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   auto rhs = static_cast<const void* const*>(B.rhs_tab.p);
   auto phi = static_cast<void* const*>(B.phi_tab.p);
   if (pl->prec == MPOIS_F64) return batch_solve(pl, rhs, 1, phi, 1, phi, 1, false, s);
@@ -1046,11 +1204,18 @@ static mpois_status check_ptrs(const mpois_plan_s* pl, const SubPlan& sp, const 
 mpois_status mpois_execute(mpois_plan pl, const void* rhs, void* phi, void* stream) {
   if (!pl || pl->subs.size() != 1) return MPOIS_ERR_INVALID;
   SubPlan& sp = pl->subs[0];
-  mpois_status st = check_ptrs(pl, sp, rhs, phi);
-  if (st != MPOIS_OK) return st;
+  // the attribute queries are host calls: repeat them only for new pointers
+  if (!(rhs && phi && rhs == pl->checked_rhs && phi == pl->checked_phi)) {
+    mpois_status st = check_ptrs(pl, sp, rhs, phi);
+    if (st != MPOIS_OK) return st;
+    pl->checked_rhs = rhs;
+    pl->checked_phi = phi;
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   pl->last_rhs = rhs;
   pl->last_phi = phi;
+  pl->last_rhs_b.clear();
+  pl->last_phi_b.clear();
   pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
   if (pl->flags & MPOIS_FLAG_PROFILE) {
     if (!pl->prof_start && hipEventCreate(&pl->prof_start) != hipSuccess) return MPOIS_ERR_DEVICE;
@@ -1083,25 +1248,66 @@ mpois_status mpois_execute(mpois_plan pl, const void* rhs, void* phi, void* stre
   return enqueue_one(pl, sp, 0, rhs, phi, s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
 }
 
-mpois_status mpois_execute_batch(mpois_plan pl, const void* const* rhs, void* const* phi, void* stream) {
-  if (!pl || !rhs || !phi) return MPOIS_ERR_INVALID;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+// Batched plans: the pointer arrays are validated and uploaded only when they
+// differ from the previous call's (pinned staging, asynchronous copy on the
+// execute's stream); with MPOIS_FLAG_GRAPH the kernel sequence is captured
+// once and replayed, since it reads the pointers from the device tables.
+static mpois_status batch_set_tables(mpois_plan_s* pl, const void* const* rhs, void* const* phi, hipStream_t s) {
+  BatchState& B = pl->batch;
   const size_t count = pl->subs.size();
+  if (B.have_tables && std::equal(rhs, rhs + count, B.staging) && std::equal(phi, phi + count, B.staging + count))
+    return MPOIS_OK;
   for (size_t i = 0; i < count; ++i) {
     mpois_status st = check_ptrs(pl, pl->subs[i], rhs[i], phi[i]);
     if (st != MPOIS_OK) return st;
   }
+  // the previous upload must have left the staging buffer before it is rewritten
+  if (B.have_tables && hipEventSynchronize(B.uploaded) != hipSuccess) return MPOIS_ERR_DEVICE;
+  B.have_tables = false;
+  for (size_t i = 0; i < count; ++i) {
+    B.staging[i] = const_cast<void*>(rhs[i]);
+    B.staging[count + i] = phi[i];
+  }
+  const size_t tb = count * sizeof(void*);
+  if (hipMemcpyAsync(B.rhs_tab.p, B.staging, tb, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(B.phi_tab.p, B.staging + count, tb, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipEventRecord(B.uploaded, s) != hipSuccess)
+    return MPOIS_ERR_DEVICE;
+  B.have_tables = true;
+  return MPOIS_OK;
+}
+
+mpois_status mpois_execute_batch(mpois_plan pl, const void* const* rhs, void* const* phi, void* stream) {
+  if (!pl || !rhs || !phi) return MPOIS_ERR_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t count = pl->subs.size();
+  if (!pl->batched) {
+    mpois_status st = check_ptrs(pl, pl->subs[0], rhs[0], phi[0]);
+    if (st != MPOIS_OK) return st;
+  } else {
+    mpois_status st = batch_set_tables(pl, rhs, phi, s);
+    if (st != MPOIS_OK) return st;
+  }
+  pl->last_rhs = nullptr;
+  pl->last_phi = nullptr;
   pl->last_rhs_b.assign(rhs, rhs + count);
   pl->last_phi_b.assign(phi, phi + count);
   pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
-  if (pl->batched) {
-    pl->batch.host_rhs.assign(rhs, rhs + count);
-    pl->batch.host_phi.assign(phi, phi + count);
-    return enqueue_batch(pl, s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
+  if (!pl->batched) return enqueue_one(pl, pl->subs[0], 0, rhs[0], phi[0], s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
+  if (pl->flags & MPOIS_FLAG_GRAPH) {
+    Graph& g = pl->graph;
+    if (!g.exec) {
+      if (hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPOIS_ERR_DEVICE;
+      hipError_t e = enqueue_batch(pl, pl->cap_stream);
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(pl->cap_stream, &graph);
+      if (e != hipSuccess || e2 != hipSuccess || !graph) return MPOIS_ERR_DEVICE;
+      g.graph = graph;
+      if (hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) return MPOIS_ERR_DEVICE;
+    }
+    return hipGraphLaunch(g.exec, s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
   }
-  for (size_t i = 0; i < count; ++i)
-    if (enqueue_one(pl, pl->subs[i], i, rhs[i], phi[i], s) != hipSuccess) return MPOIS_ERR_DEVICE;
-  return MPOIS_OK;
+  return enqueue_batch(pl, s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
 }
 
 mpois_status mpois_get_info(mpois_plan pl, void* stream, mpois_info* out) {

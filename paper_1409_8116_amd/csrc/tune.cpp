@@ -1,9 +1,8 @@
-// Kernel-shape autotuner: for one line pass, time every kernel shape that can
-// hold it and keep the fastest.  Results are kept per process and, when the
-// environment variable MPOIS_TUNE_CACHE names a file, in that file as lines
-//   <device name> <key> <shape id>
-// so later processes reuse them.  A line for another device, or one that names
-// a shape that cannot hold the pass, is ignored.
+// Autotuner measurements and decision cache.  The plan layer enumerates the
+// candidates of a line pass (kernel shapes that can hold it, and alternative
+// radix plans of its DFT length: other stage orders and splits, a Bluestein
+// convolution instead of a Rader stage or a large odd radix), times each with
+// tune_time on scratch arrays, and keeps the fastest.
 #include "tune.h"
 
 #include <hip/hip_runtime.h>
@@ -19,30 +18,112 @@
 
 #include "mpois.h"
 
+#ifndef MPOIS_BUILD_ID
+#define MPOIS_BUILD_ID "dev"
+#endif
+
 namespace mpois {
-int num_kernel_cfgs();
-void kernel_cfg(int i, int* f64, int* np, int* nt, int* pmax);
-int kernel_cfg_rader(int i);
-int kernel_cfg_slim(int i);
-size_t line_pass_lds(int cfg, int n, int P);
 hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s);
 
 bool tune_enabled(unsigned flags) { return (flags & MPOIS_FLAG_TUNE) != 0; }
 
+struct TuneSession {
+  void* src = nullptr;
+  void* dst = nullptr;
+  size_t bytes = 0;
+  double* shift = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = false;
+};
+
+TuneSession* tune_begin() {
+  TuneSession* t = new TuneSession();
+  t->ok = hipStreamCreateWithFlags(&t->s, hipStreamNonBlocking) == hipSuccess &&
+          hipEventCreate(&t->e0) == hipSuccess && hipEventCreate(&t->e1) == hipSuccess &&
+          hipMalloc(reinterpret_cast<void**>(&t->shift), 64) == hipSuccess &&
+          hipMemsetAsync(t->shift, 0, 64, t->s) == hipSuccess;
+  if (!t->ok) (void)hipGetLastError();
+  return t;
+}
+
+void tune_end(TuneSession* t) {
+  if (!t) return;
+  if (t->s) (void)hipStreamSynchronize(t->s);
+  if (t->src) (void)hipFree(t->src);
+  if (t->dst) (void)hipFree(t->dst);
+  if (t->shift) (void)hipFree(t->shift);
+  if (t->e0) (void)hipEventDestroy(t->e0);
+  if (t->e1) (void)hipEventDestroy(t->e1);
+  if (t->s) (void)hipStreamDestroy(t->s);
+  (void)hipGetLastError();
+  delete t;
+}
+
+// Scratch of at least `bytes` per array, zero-filled (grown, never shrunk,
+// within a session).
+static bool ensure_scratch(TuneSession* t, size_t bytes) {
+  if (bytes <= t->bytes) return true;
+  (void)hipStreamSynchronize(t->s);
+  if (t->src) (void)hipFree(t->src);
+  if (t->dst) (void)hipFree(t->dst);
+  t->src = t->dst = nullptr;
+  t->bytes = 0;
+  if (hipMalloc(&t->src, bytes) != hipSuccess || hipMalloc(&t->dst, bytes) != hipSuccess ||
+      hipMemsetAsync(t->src, 0, bytes, t->s) != hipSuccess || hipMemsetAsync(t->dst, 0, bytes, t->s) != hipSuccess) {
+    (void)hipGetLastError();
+    if (t->src) (void)hipFree(t->src);
+    if (t->dst) (void)hipFree(t->dst);
+    t->src = t->dst = nullptr;
+    return false;
+  }
+  t->bytes = bytes;
+  return true;
+}
+
+double tune_time(TuneSession* t, const PassArgs& proto, int cfg, int64_t lines) {
+  if (!t || !t->ok) return -1.0;
+  const size_t es = 8;  // scratch sized for double, valid for either element type
+  const int64_t nl = lines > 0 ? lines : proto.nlines;
+  if (!ensure_scratch(t, size_t(nl) * size_t(proto.ax.n) * es)) return -1.0;
+  PassArgs a = proto;
+  a.nlines = nl;
+  // a pass over nl lines of a (nl / inner, n, inner) box keeps its stride class
+  if (a.inner > 1 && nl % a.inner != 0) a.inner = 1;
+  a.src = t->src;
+  a.dst = t->dst;
+  a.update = 0;
+  a.shift = t->shift;
+  a.lam_a = nullptr;  // eigenvalue tables of the other axes belong to the real box
+  a.lam_b = nullptr;
+  bool ok = launch_line_pass(cfg, a, t->s) == hipSuccess;  // warm-up
+  ok = ok && hipEventRecord(t->e0, t->s) == hipSuccess;
+  constexpr int kReps = 3;
+  for (int r = 0; r < kReps && ok; ++r) ok = launch_line_pass(cfg, a, t->s) == hipSuccess;
+  ok = ok && hipEventRecord(t->e1, t->s) == hipSuccess && hipEventSynchronize(t->e1) == hipSuccess;
+  float ms = 0.f;
+  if (!ok || hipEventElapsedTime(&ms, t->e0, t->e1) != hipSuccess) {
+    (void)hipGetLastError();
+    return -1.0;
+  }
+  return double(ms) / kReps;
+}
+
 namespace {
 
 std::mutex g_mu;
-std::map<std::string, int> g_cache;
+std::map<std::string, std::pair<int, int>> g_cache;
 bool g_loaded = false;
 
-std::string device_name() {
-  int dev = 0;
+std::string device_key() {
+  int dev = 0, rt = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  (void)hipRuntimeGetVersion(&rt);
   std::string s = prop.gcnArchName;
   for (auto& c : s)
-    if (c == ' ') c = '_';
-  return s + "_cu" + std::to_string(prop.multiProcessorCount);
+    if (c == ' ' || c == ':') c = '_';
+  return s + "_cu" + std::to_string(prop.multiProcessorCount) + "_hip" + std::to_string(rt) + "_" + MPOIS_BUILD_ID;
 }
 
 void load_file() {
@@ -51,95 +132,35 @@ void load_file() {
   const char* path = std::getenv("MPOIS_TUNE_CACHE");
   if (!path) return;
   std::ifstream in(path);
-  const std::string dev = device_name();
+  const std::string dev = device_key();
   std::string line;
   while (std::getline(in, line)) {
     std::istringstream ss(line);
     std::string d, key;
-    int cfg = -1;
-    if (ss >> d >> key >> cfg && d == dev && cfg >= 0 && cfg < num_kernel_cfgs()) g_cache[key] = cfg;
+    int a = -1, b = -1;
+    if (ss >> d >> key >> a >> b && d == dev) g_cache[key] = {a, b};
   }
-}
-
-void save_entry(const std::string& key, int cfg) {
-  const char* path = std::getenv("MPOIS_TUNE_CACHE");
-  if (!path) return;
-  std::ofstream out(path, std::ios::app);
-  if (out) out << device_name() << " " << key << " " << cfg << "\n";
-}
-
-bool fits(int cfg, bool f64, int n, int P, bool rader, bool odd) {
-  int cf64, np, nt, pmax;
-  kernel_cfg(cfg, &cf64, &np, &nt, &pmax);
-  if ((cf64 != 0) != f64 || P > pmax) return false;
-  if (rader && !kernel_cfg_rader(cfg)) return false;
-  if (odd && kernel_cfg_slim(cfg)) return false;
-  return line_pass_lds(cfg, n, P) <= size_t(160 * 1024);
 }
 
 }  // namespace
 
-int tune_pass(const PassArgs& proto, int fallback, bool f64, bool rader, bool odd) {
-  const int n = proto.ax.n, P = proto.ax.P;
-  std::ostringstream k;
-  k << (f64 ? "f64" : "f32") << "/kf" << proto.kind_f << "/kb" << proto.kind_b << "/n" << n << "/P" << P << "/lines"
-    << proto.nlines << "/inner" << proto.inner;
-  const std::string key = k.str();
+bool tune_lookup(const std::string& key, int* a, int* b) {
   std::lock_guard<std::mutex> lock(g_mu);
   load_file();
   auto it = g_cache.find(key);
-  if (it != g_cache.end() && fits(it->second, f64, n, P, rader, odd)) return it->second;
+  if (it == g_cache.end()) return false;
+  *a = it->second.first;
+  *b = it->second.second;
+  return true;
+}
 
-  std::vector<int> cands;
-  for (int i = 0; i < num_kernel_cfgs(); ++i)
-    if (fits(i, f64, n, P, rader, odd)) cands.push_back(i);
-  if (cands.size() <= 1) return cands.empty() ? fallback : cands[0];
-
-  // scratch arrays of the pass's own size (values do not affect the timing)
-  const size_t elems = size_t(proto.nlines) * size_t(n);
-  const size_t es = f64 ? 8 : 4;
-  void *src = nullptr, *dst = nullptr;
-  double* shift = nullptr;
-  hipStream_t s = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  int best = fallback;
-  if (hipMalloc(&src, elems * es) == hipSuccess && hipMalloc(&dst, elems * es) == hipSuccess &&
-      hipMalloc(reinterpret_cast<void**>(&shift), 64) == hipSuccess &&
-      hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
-      hipEventCreate(&e1) == hipSuccess && hipMemsetAsync(src, 0, elems * es, s) == hipSuccess &&
-      hipMemsetAsync(shift, 0, 64, s) == hipSuccess) {
-    PassArgs a = proto;
-    a.src = src;
-    a.dst = dst;
-    a.src_f64 = f64 ? 1 : 0;
-    a.dst_f64 = f64 ? 1 : 0;
-    a.update = 0;
-    a.shift = shift;
-    float best_ms = 1e30f;
-    for (int cfg : cands) {
-      bool ok = launch_line_pass(cfg, a, s) == hipSuccess;  // warm-up
-      ok = ok && hipEventRecord(e0, s) == hipSuccess;
-      for (int r = 0; r < 3 && ok; ++r) ok = launch_line_pass(cfg, a, s) == hipSuccess;
-      ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-      float ms = 0.f;
-      if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
-        best_ms = ms;
-        best = cfg;
-      }
-    }
-    if (std::getenv("MPOIS_LOG")) std::fprintf(stderr, "[mpois tune] %s -> shape %d (%.3f ms)\n", key.c_str(), best,
-                                               best_ms / 3);
-  }
-  (void)hipGetLastError();
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  if (s) (void)hipStreamDestroy(s);
-  if (src) (void)hipFree(src);
-  if (dst) (void)hipFree(dst);
-  if (shift) (void)hipFree(shift);
-  g_cache[key] = best;
-  save_entry(key, best);
-  return best;
+void tune_store(const std::string& key, int a, int b) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_cache[key] = {a, b};
+  const char* path = std::getenv("MPOIS_TUNE_CACHE");
+  if (!path) return;
+  std::ofstream out(path, std::ios::app);
+  if (out) out << device_key() << " " << key << " " << a << " " << b << "\n";
 }
 
 }  // namespace mpois

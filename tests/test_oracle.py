@@ -343,3 +343,17 @@ def test_a_planted_index_shift_is_caught(monkeypatch):
     g = np.random.default_rng(1).standard_normal(6)
     ref, _ = oracle.lu_solve(g, axes)
     assert np.max(np.abs(oracle.solve(g, axes, "fd") - ref)) > 1e-3 * np.max(np.abs(ref))
+
+
+def test_generated_singular_rhs_are_compatible():
+    """The seeded inputs of singular problems have zero weighted mean, so the
+    solve does not have to project them (Neumann cube, 2D batch entries)."""
+    import workloads
+    d, g = workloads.neumann_blobs(24, seed=3)
+    axes = oracle.axes_from(d["shape"], d["h"], d["bc"], d["grid"])
+    assert abs(oracle.weighted_mean(g, axes)) <= 1e-15 * np.abs(g).max()
+    for i, dd in enumerate(workloads.batch_2d(count=40, lo=5, hi=30, seed=4)):
+        gi = workloads.batch_rhs(dd, i)
+        if all(b in ("P", "N") for b in dd["bc"]):
+            ax = oracle.axes_from(dd["shape"], dd["h"], dd["bc"], dd["grid"])
+            assert abs(oracle.weighted_mean(gi, ax)) <= 1e-14, (i, dd)

@@ -33,6 +33,20 @@ def _is_singular(d):
     return all(b in ("P", "N") for b in d["bc"])
 
 
+def remove_weighted_mean(g, d):
+    """g minus its weighted mean, the mean that makes a right-hand side of a
+    singular problem (every axis periodic or Neumann) compatible: node weights
+    are the product over axes of 1/2 at both end nodes of a vertex-grid
+    Neumann axis and 1 elsewhere (the trapezoid rule on those axes)."""
+    w = np.ones((), dtype=np.float64)
+    for n, b, gr in zip(d["shape"], d["bc"], d["grid"]):
+        wd = np.ones(n)
+        if b == "N" and gr == "v" and n >= 2:
+            wd[0] = wd[-1] = 0.5
+        w = np.multiply.outer(w, wd)
+    return g - float((w * g).sum() / w.sum())
+
+
 # --------------------------------------------------------------------------- periodic box
 def periodic_noise(n=32, seed=1):
     """n^3 periodic box, FD, h = 1/n; g ~ U(-1, 1) with its mean subtracted."""
@@ -81,7 +95,8 @@ def neumann_blobs(n=512, seed=3, n_blobs=64, sigma=0.02):
     """n^3 vertex-grid all-Neumann cube on [0,1]^3, FD, h = 1/(n-1).
 
     g = sum_c a_c exp(-|x - x_c|^2 / (2 sigma^2)), x_c ~ U[0,1]^3, a_c ~ N(0,1),
-    evaluated separably at x_j = j/(n-1); the arithmetic mean is subtracted.
+    evaluated separably at x_j = j/(n-1); the trapezoid-weighted mean (end
+    nodes weighted 1/2 on every axis) is subtracted, so g is compatible.
     """
     h = 1.0 / (n - 1)
     d = desc((n, n, n), (h,) * 3, ("N",) * 3, ("v",) * 3, "fd")
@@ -94,8 +109,7 @@ def neumann_blobs(n=512, seed=3, n_blobs=64, sigma=0.02):
     gz = np.exp(-(x[None, :] - centres[:, 2:3]) ** 2 / (2 * sigma * sigma))
     yz = (gy[:, :, None] * gz[:, None, :]).reshape(n_blobs, n * n)
     g = ((gx * amps[:, None]).T @ yz).reshape(n, n, n)
-    g -= g.mean()
-    return d, g
+    return d, remove_weighted_mean(g, d)
 
 
 # --------------------------------------------------------------------------- 2D batch
@@ -122,11 +136,12 @@ def batch_2d(count=2048, lo=64, hi=1024, seed=4):
 
 
 def batch_rhs(d, i, seed=4):
-    """g_i ~ N(0, 1) for problem i of a batch; arithmetic mean removed when singular."""
+    """g_i ~ N(0, 1) for problem i of a batch; when the problem is singular its
+    weighted mean (remove_weighted_mean) is removed, so g_i is compatible."""
     rng = np.random.default_rng([seed, i])
     g = rng.standard_normal(d["shape"])
     if _is_singular(d):
-        g -= g.mean()
+        g = remove_weighted_mean(g, d)
     return g
 
 
