@@ -109,6 +109,25 @@ mpois_status mpois_plan_create_batch(const mpois_grid_desc* grids, int count, in
  * elsewhere) and has zero weighted mean. */
 mpois_status mpois_execute(mpois_plan plan, const void* rhs, void* phi, void* stream);
 
+/* Largest scratch the allocation-free execute uses (bytes per device). */
+#define MPOIS_NOALLOC_SCRATCH_BYTES (65u << 20)
+
+/* For callers that cannot allocate device memory while they run (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve as mpois_execute, but the scratch its kernels use -- the FP32
+ * working array of an MPOIS_F32_REFINE plan (4 bytes per grid point), the
+ * residual block partial sums and the reduced scalars -- lives in a static
+ * device array of the library (MPOIS_NOALLOC_SCRATCH_BYTES, one copy per
+ * device, held until the process ends) instead of the plan's workspace.
+ * Allocates nothing and never synchronises; the plan's flags for graph
+ * capture and profiling are ignored (it always enqueues its kernels).
+ * Refinement plans up to 16,908,224 grid points (256^3 included) fit;
+ * larger ones return UNSUPPORTED.  The plan must belong to the current device (else DEVICE).
+ * All calls on one device share its scratch: calls that overlap in time on
+ * one device (different streams, or other host threads) race and must be
+ * serialised by the caller.  mpois_get_info reports on the last call. */
+mpois_status mpois_execute_noalloc(mpois_plan plan, const void* rhs, void* phi, void* stream);
+
 /* Solve every grid of a batch plan: rhs[i], phi[i] are the device arrays of
  * grid i (host arrays of `count` device pointers). */
 mpois_status mpois_execute_batch(mpois_plan plan, const void* const* rhs, void* const* phi, void* stream);

@@ -72,6 +72,7 @@ def load_library():
                                             ctypes.c_double, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(P)]
     lib.mpois_execute.argtypes = [P, P, P, P]
     lib.mpois_execute_batch.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
+    lib.mpois_execute_noalloc.argtypes = [P, P, P, P]
     lib.mpois_get_info.argtypes = [P, P, ctypes.POINTER(Info)]
     lib.mpois_destroy.argtypes = [P]
     lib.mpois_workspace_bytes.argtypes = [P]
@@ -87,6 +88,7 @@ def load_library():
         [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.mpois_kernel_shape.argtypes = [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
     for name in ("mpois_kernel_shape", "mpois_plan_create", "mpois_plan_create_batch", "mpois_execute", "mpois_execute_batch",
+                 "mpois_execute_noalloc",
                  "mpois_get_info", "mpois_destroy", "mpois_validate", "mpois_axis_eigenvalues", "mpois_axis_plan",
                  "mpois_profile"):
         getattr(lib, name).restype = ctypes.c_int
@@ -205,6 +207,17 @@ class Plan:
                                     _stream_ptr(stream))
         if st:
             raise MpoisError(st, "mpois_execute")
+        return phi
+
+    def solve_noalloc(self, rhs, phi, stream=None):
+        """mpois_execute_noalloc: the same solve with the library's static
+        device scratch instead of the plan's workspace (allocates nothing)."""
+        _check_tensor(rhs, self.shape, self.dtype, "rhs")
+        _check_tensor(phi, self.shape, self.dtype, "phi")
+        st = self.lib.mpois_execute_noalloc(self._h, ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(phi.data_ptr()),
+                                            _stream_ptr(stream))
+        if st:
+            raise MpoisError(st, "mpois_execute_noalloc")
         return phi
 
     def info(self, stream=None, check=False):

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -931,15 +932,28 @@ hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, 
   return hipSuccess;
 }
 
+// Scratch of one single-grid execute: the FP32 working array of refinement
+// plans, the residual kernel's block partial sums (kMaxResidBlocks x 4) and
+// the reduced scalars (S_COUNT per grid).
+struct Workspace {
+  void* work;
+  double* partials;
+  double* scalars;
+};
+
+Workspace plan_workspace(mpois_plan_s* pl) {
+  return {pl->work.p, static_cast<double*>(pl->partials.p), static_cast<double*>(pl->scalars.p)};
+}
+
 hipError_t run_resid(mpois_plan_s* pl, SubPlan& sp, const void* rhs, const void* phi, void* r, int r_f64,
-                     const double* mg, double* scalars, hipStream_t s) {
+                     const double* mg, double* scalars, hipStream_t s, double* partials = nullptr) {
   ResidArgs a = sp.resid;
   a.phi = static_cast<const double*>(phi);
   a.g = static_cast<const double*>(rhs);
   a.r = r;
   a.r_f64 = r_f64;
   a.mg = mg;
-  a.partials = static_cast<double*>(pl->partials.p);
+  a.partials = partials ? partials : static_cast<double*>(pl->partials.p);
   hipError_t e = launch_resid(a, s);
   if (e != hipSuccess) return e;
   prof_mark(pl, 100, double(sp.npts) * (phi ? 16 : 8) + (r ? double(sp.npts) * (r_f64 ? 8 : 4) : 0), s);
@@ -949,21 +963,24 @@ hipError_t run_resid(mpois_plan_s* pl, SubPlan& sp, const void* rhs, const void*
   return hipSuccess;
 }
 
-hipError_t enqueue_one(mpois_plan_s* pl, SubPlan& sp, size_t sub_index, const void* rhs, void* phi, hipStream_t s) {
+hipError_t enqueue_one(mpois_plan_s* pl, SubPlan& sp, size_t sub_index, const void* rhs, void* phi, hipStream_t s,
+                       const Workspace& ws) {
   if (pl->prec == MPOIS_F64) return run_solve(pl, sp, rhs, 1, phi, 1, phi, 1, false, nullptr, s);
   if (pl->prec == MPOIS_F32) return run_solve(pl, sp, rhs, 0, phi, 0, phi, 0, false, nullptr, s);
   // FP32 solve, then fixed number of FP64-residual corrections.
-  double* sc = static_cast<double*>(pl->scalars.p) + sub_index * S_COUNT;
-  void* work = pl->work.p;
+  double* sc = ws.scalars + sub_index * S_COUNT;
+  void* work = ws.work;
   hipError_t e;
   if (sp.singular) {
     // m_g = sum w g / sum w, so the FP32 residual carries no large constant.
-    if ((e = run_resid(pl, sp, rhs, nullptr, nullptr, 0, nullptr, sc, s)) != hipSuccess) return e;
+    if ((e = run_resid(pl, sp, rhs, nullptr, nullptr, 0, nullptr, sc, s, ws.partials)) != hipSuccess) return e;
   }
   if ((e = run_solve(pl, sp, rhs, 1, phi, 1, work, 0, false, nullptr, s)) != hipSuccess) return e;
   for (int it = 0; it < pl->max_iter; ++it) {
     // r = g - m_g - L phi (FP64, stored FP32), sum w phi -> gauge shift
-    if ((e = run_resid(pl, sp, rhs, phi, work, 0, sp.singular ? sc + S_MG : nullptr, sc, s)) != hipSuccess) return e;
+    if ((e = run_resid(pl, sp, rhs, phi, work, 0, sp.singular ? sc + S_MG : nullptr, sc, s, ws.partials)) !=
+        hipSuccess)
+      return e;
     // phi <- phi + delta, minus the weighted mean of phi when the problem is singular
     if ((e = run_solve(pl, sp, work, 0, phi, 1, work, 0, true, sp.singular ? sc + S_SHIFT : nullptr, s)) != hipSuccess)
       return e;
@@ -1222,7 +1239,7 @@ mpois_status mpois_execute(mpois_plan pl, const void* rhs, void* phi, void* stre
     pl->prof_used = 0;
     pl->profiling = true;
     (void)hipEventRecord(pl->prof_start, s);
-    const hipError_t e = enqueue_one(pl, sp, 0, rhs, phi, s);
+    const hipError_t e = enqueue_one(pl, sp, 0, rhs, phi, s, plan_workspace(pl));
     pl->profiling = false;
     return e == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
   }
@@ -1234,7 +1251,7 @@ mpois_status mpois_execute(mpois_plan pl, const void* rhs, void* phi, void* stre
       g.exec = nullptr;
       g.graph = nullptr;
       if (hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPOIS_ERR_DEVICE;
-      hipError_t e = enqueue_one(pl, sp, 0, rhs, phi, pl->cap_stream);
+      hipError_t e = enqueue_one(pl, sp, 0, rhs, phi, pl->cap_stream, plan_workspace(pl));
       hipGraph_t graph = nullptr;
       hipError_t e2 = hipStreamEndCapture(pl->cap_stream, &graph);
       if (e != hipSuccess || e2 != hipSuccess || !graph) return MPOIS_ERR_DEVICE;
@@ -1245,7 +1262,7 @@ mpois_status mpois_execute(mpois_plan pl, const void* rhs, void* phi, void* stre
     }
     return hipGraphLaunch(g.exec, s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
   }
-  return enqueue_one(pl, sp, 0, rhs, phi, s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
+  return enqueue_one(pl, sp, 0, rhs, phi, s, plan_workspace(pl)) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
 }
 
 // Batched plans: the pointer arrays are validated and uploaded only when they
@@ -1277,6 +1294,70 @@ static mpois_status batch_set_tables(mpois_plan_s* pl, const void* const* rhs, v
   return MPOIS_OK;
 }
 
+// ---------------------------------------------------------------------------- allocation-free execute
+// Static scratch of mpois_execute_noalloc: every device the library runs on
+// holds one copy until the process ends.  Layout: reduced scalars (256 B),
+// residual block partial sums (kMaxResidBlocks x 4 doubles), then the FP32
+// working array of a refinement plan.  Host code must not pass `scratch`
+// itself to a kernel (its host-side name is not a device address): the
+// per-device address comes from hipGetSymbolAddress.
+constexpr size_t kNoallocScalars = 256;
+constexpr size_t kNoallocPartials = size_t(kMaxResidBlocks) * 4 * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[MPOIS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, looked up once per device with
+// that device current (the caller's current device).
+static mpois_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return MPOIS_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return MPOIS_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MPOIS_OK;
+}
+
+mpois_status mpois_execute_noalloc(mpois_plan pl, const void* rhs, void* phi, void* stream) {
+  if (!pl || pl->subs.size() != 1) return MPOIS_ERR_INVALID;
+  SubPlan& sp = pl->subs[0];
+  const size_t work_bytes = pl->prec == MPOIS_F32_REFINE ? size_t(sp.npts) * sizeof(float) : 0;
+  if (kNoallocScalars + kNoallocPartials + work_bytes > size_t(MPOIS_NOALLOC_SCRATCH_BYTES))
+    return MPOIS_ERR_UNSUPPORTED;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pl->device) return MPOIS_ERR_DEVICE;
+  if (!(rhs && phi && rhs == pl->checked_rhs && phi == pl->checked_phi)) {
+    mpois_status st = check_ptrs(pl, sp, rhs, phi);
+    if (st != MPOIS_OK) return st;
+    pl->checked_rhs = rhs;
+    pl->checked_phi = phi;
+  }
+  void* base = nullptr;
+  mpois_status st = scratch_address(dev, &base);
+  if (st != MPOIS_OK) return st;
+  // nothing in the scratch has to start at zero: the residual kernel writes
+  // every partial the reduction reads, the reduction writes every scalar it
+  // later reads, and the first sweep writes the working array before use
+  char* b = static_cast<char*>(base);
+  Workspace ws{b + kNoallocScalars + kNoallocPartials, reinterpret_cast<double*>(b + kNoallocScalars),
+               reinterpret_cast<double*>(b)};
+  pl->last_rhs = rhs;
+  pl->last_phi = phi;
+  pl->last_rhs_b.clear();
+  pl->last_phi_b.clear();
+  pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
+  return enqueue_one(pl, sp, 0, rhs, phi, static_cast<hipStream_t>(stream), ws) == hipSuccess ? MPOIS_OK
+                                                                                              : MPOIS_ERR_DEVICE;
+}
+
 mpois_status mpois_execute_batch(mpois_plan pl, const void* const* rhs, void* const* phi, void* stream) {
   if (!pl || !rhs || !phi) return MPOIS_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1293,7 +1374,7 @@ mpois_status mpois_execute_batch(mpois_plan pl, const void* const* rhs, void* co
   pl->last_rhs_b.assign(rhs, rhs + count);
   pl->last_phi_b.assign(phi, phi + count);
   pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
-  if (!pl->batched) return enqueue_one(pl, pl->subs[0], 0, rhs[0], phi[0], s) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
+  if (!pl->batched) return enqueue_one(pl, pl->subs[0], 0, rhs[0], phi[0], s, plan_workspace(pl)) == hipSuccess ? MPOIS_OK : MPOIS_ERR_DEVICE;
   if (pl->flags & MPOIS_FLAG_GRAPH) {
     Graph& g = pl->graph;
     if (!g.exec) {
