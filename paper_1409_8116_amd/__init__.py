@@ -148,6 +148,8 @@ def kernel_shape_name(cfg):
     if st:
         return f"line_pass#{cfg}"
     t = "double" if v[0].value == 8 else "float"
+    if cfg >= 200:
+        return f"line_pass_spec<{t}, {v[1].value}, {v[2].value}, n={v[3].value}>"
     return f"line_pass<{t}, {v[1].value}, {v[2].value}, {v[3].value}>"
 
 

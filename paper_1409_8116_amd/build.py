@@ -11,7 +11,16 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpois.so")
 SOURCES = ["aux.hip", "dispatch.cpp", "mpois.cpp", "tune.cpp"]
-NUM_SHAPES = 16  # entries of cfgs.h (MPOIS_NUM_CFGS); lp_inst.hip is compiled once per shape
+def _count(header, macro):
+    import re
+    with open(os.path.join(CSRC, header)) as fh:
+        return int(re.search(r"#define\s+" + macro + r"\s+(\d+)", fh.read()).group(1))
+
+
+# lp_inst.hip is compiled once per generic shape (cfgs.h), sp_inst.hip once per
+# specialised kernel (specs.h)
+NUM_SHAPES = _count("cfgs.h", "MPOIS_NUM_CFGS")
+NUM_SPECS = _count("specs.h", "MPOIS_NUM_SPECS")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in device code
@@ -49,6 +58,12 @@ def build(verbose=False, jobs=None, incremental=False):
         if incremental and os.path.exists(obj) and os.path.getmtime(obj) > newest:
             continue
         cmds.append([HIPCC] + FLAGS + [f"-DMPOIS_CFG={i}", "-c", os.path.join(CSRC, "lp_inst.hip"), "-o", obj])
+    for i in range(NUM_SPECS):
+        obj = os.path.join(objdir, f"sp_inst_{i}.o")
+        objs.append(obj)
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > newest:
+            continue
+        cmds.append([HIPCC] + FLAGS + [f"-DMPOIS_SPEC={i}", "-c", os.path.join(CSRC, "sp_inst.hip"), "-o", obj])
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)

@@ -1,8 +1,11 @@
 // Kernel-shape table and dispatch of the line-transform kernel.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "cfgs.h"
 #include "internal.h"
+#include "specs.h"
 
 namespace mpois {
 
@@ -16,7 +19,29 @@ MPOIS_DECL(7) MPOIS_DECL(8) MPOIS_DECL(9) MPOIS_DECL(10) MPOIS_DECL(11) MPOIS_DE
 MPOIS_DECL(14) MPOIS_DECL(15)
 #undef MPOIS_DECL
 
+// one pair per specialised kernel, defined in sp_inst.hip compiled with MPOIS_SPEC = id
+#define MPOIS_DECL_SPEC(ID, ...)                                                    \
+  hipError_t launch_spec_##ID(const PassArgs& a, hipStream_t s, size_t lds); \
+  hipError_t prepare_spec_##ID();
+MPOIS_SPECS(MPOIS_DECL_SPEC)
+#undef MPOIS_DECL_SPEC
+
 namespace {
+struct SpecInfo {
+  int f64, np, nt, rader, n, M, P, kf, kb;
+  std::vector<int> radices;
+  hipError_t (*launch)(const PassArgs&, hipStream_t, size_t);
+  hipError_t (*prepare)();
+};
+const SpecInfo kSpecs[] = {
+#define X(ID, T, NP, NT, RADER, SLIM, N, M, P, KF, KB, ...) \
+  {sizeof(T) == 8, NP, NT, RADER, N, M, P, KF, KB, {__VA_ARGS__}, &launch_spec_##ID, &prepare_spec_##ID},
+    MPOIS_SPECS(X)
+#undef X
+};
+constexpr int kNumSpecs = sizeof(kSpecs) / sizeof(kSpecs[0]);
+static_assert(kNumSpecs == MPOIS_NUM_SPECS, "spec list and count disagree");
+
 struct KernelCfg {
   int f64, np, nt, pmax, rader, slim;
 };
@@ -68,7 +93,47 @@ hipError_t prepare_kernels() {
     hipError_t e = kPrepare[i]();
     if (e != hipSuccess) return e;
   }
+  for (int i = 0; i < kNumSpecs; ++i) {
+    hipError_t e = kSpecs[i].prepare();
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
+}
+
+int num_specs() { return kNumSpecs; }
+
+// Specialised kernel for a pass with these parameters, or -1.
+int find_spec(bool f64, int n, int M, int P, int kind_f, int kind_b, const std::vector<int>& radices) {
+  for (int i = 0; i < kNumSpecs; ++i) {
+    const SpecInfo& c = kSpecs[i];
+    if ((c.f64 != 0) == f64 && c.n == n && c.M == M && c.P == P && c.kf == kind_f && c.kb == kind_b &&
+        c.radices == radices)
+      return i;
+  }
+  return -1;
+}
+
+void spec_shape(int i, int* f64, int* np, int* nt, int* n) {
+  *f64 = kSpecs[i].f64;
+  *np = kSpecs[i].np;
+  *nt = kSpecs[i].nt;
+  *n = kSpecs[i].n;
+}
+
+// LDS of a specialised kernel: rows of ZP = NP + 1 complex values (the
+// padded pitch of spec_pitch in line_pass.h), n real rows or P complex rows.
+size_t spec_lds(int i) {
+  const SpecInfo& c = kSpecs[i];
+  const size_t es = c.f64 ? 8 : 4;
+  const size_t zp = size_t(c.np) + 1;
+  const size_t xs = 2 * zp * size_t(c.n);
+  const size_t zs = 2 * zp * size_t(c.P);
+  return (xs > zs ? xs : zs) * es;
+}
+
+hipError_t launch_spec(int i, const PassArgs& a, hipStream_t s) {
+  if (i < 0 || i >= kNumSpecs) return hipErrorInvalidValue;
+  return kSpecs[i].launch(a, s, spec_lds(i));
 }
 
 hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s) {

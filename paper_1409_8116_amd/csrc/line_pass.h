@@ -43,6 +43,31 @@ __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
 template <typename T>
 __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.im, -a.re}; }
 
+// Length view of one axis transform.  Ax<> reads the line length n, the
+// complex DFT length M and the work length P (P > M: Bluestein) from the
+// device description at run time; Ax<N, M, P> makes them compile-time
+// constants, so a kernel specialised for one length folds its index
+// arithmetic and sizes its loops exactly.  Table pointers always come from
+// the description.
+template <int N_ = 0, int M_ = 0, int P_ = 0>
+struct Ax {
+  const AxisDev& d;
+  static constexpr bool ct = N_ != 0;
+  static constexpr int Nc = N_, Mc = M_, Pc = P_;
+  __device__ __forceinline__ int n() const {
+    if constexpr (ct) return N_; else return d.n;
+  }
+  __device__ __forceinline__ int M() const {
+    if constexpr (ct) return M_; else return d.M;
+  }
+  __device__ __forceinline__ int P() const {
+    if constexpr (ct) return P_; else return d.P;
+  }
+  __device__ __forceinline__ bool blue() const {
+    if constexpr (ct) return P_ != M_; else return d.bluestein != 0;
+  }
+};
+
 // Thread index hidden from loop-invariant code motion: per-item address
 // arithmetic is then recomputed where it is used instead of being hoisted out
 // of the phase / stage loops and kept live (which spills).
@@ -276,12 +301,17 @@ __device__ __forceinline__ void dft_any(cx<T>* v) {
 }
 
 // ----------------------------------------------------------------------------- Stockham stage
-// Work buffer layout: Z[m * NP + p] holds element m of pair p.  All butterflies
+// Work buffer layout: Z[m * ZP + p] holds element m of pair p (ZP >= NP: the
+// row pitch in complex values; a pitch above NP staggers the rows over the
+// LDS banks).  All butterflies
 // of the stage are read into registers before the barrier and written after
 // it, so the stage runs in place in one buffer.
-template <typename T, int R, int NP, int NT, int PMAX>
-__device__ __forceinline__ void stage(cx<T>* Z, int P, int ns, const cx<T>* __restrict__ tw) {
-  constexpr int NB = ((PMAX / R) * NP + NT - 1) / NT;
+// PC, NSC: compile-time work length and stage stride (0: the run-time P, ns).
+template <typename T, int R, int NP, int NT, int PMAX, int PC = 0, int NSC = 0, int ZP = NP>
+__device__ __forceinline__ void stage(cx<T>* Z, int P_rt, int ns_rt, const cx<T>* __restrict__ tw) {
+  constexpr int NB = (((PC ? PC : PMAX) / R) * NP + NT - 1) / NT;
+  const int P = PC ? PC : P_rt;
+  const int ns = NSC ? NSC : ns_rt;
   const int nbp = P / R;      // butterflies per pair
   const int items = nbp * NP;
   const int tid = opaque_tid();
@@ -293,7 +323,7 @@ __device__ __forceinline__ void stage(cx<T>* Z, int P, int ns, const cx<T>* __re
       const int p = item % NP;
       const int b = item / NP;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = Z[(b + r * nbp) * NP + p];
+      for (int r = 0; r < R; ++r) v[i][r] = Z[(b + r * nbp) * ZP + p];
       if (ns > 1) {
         const int k = b % ns;
         const cx<T>* w = tw + k * (R - 1);
@@ -314,7 +344,7 @@ __device__ __forceinline__ void stage(cx<T>* Z, int P, int ns, const cx<T>* __re
       const int k = b % ns;
       const int base = (b - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) Z[(base + r * ns) * NP + p] = v[i][r];
+      for (int r = 0; r < R; ++r) Z[(base + r * ns) * ZP + p] = v[i][r];
     }
   }
   __syncthreads();
@@ -406,12 +436,14 @@ __device__ __forceinline__ int lane_bitrev(int s) {
 // two.  tab holds dhat (72 values, DFT_72(d)/72) then e^{-2 pi i j/72}, j < 72.
 // Every lane of a round runs the arithmetic (idle groups on zeros) so each
 // lane move has its partner; rounds with no work at all are skipped.
-template <typename T, int NP, int NT, int PMAX, int G>
-__device__ __forceinline__ void stage_rader73(cx<T>* Z, int P, int ns, const cx<T>* __restrict__ tw,
+template <typename T, int NP, int NT, int PMAX, int G, int PC = 0, int NSC = 0, int ZP = NP>
+__device__ __forceinline__ void stage_rader73(cx<T>* Z, int P_rt, int ns_rt, const cx<T>* __restrict__ tw,
                                               const cx<T>* __restrict__ tab) {
   static_assert(G == 2 || G == 4 || G == 8, "lanes per Rader butterfly");
   constexpr int R = 73, L = 72, K = L / G;
-  constexpr int NBG = ((PMAX / R) * NP * G + NT - 1) / NT;
+  constexpr int NBG = (((PC ? PC : PMAX) / R) * NP * G + NT - 1) / NT;
+  const int P = PC ? PC : P_rt;
+  const int ns = NSC ? NSC : ns_rt;
   constexpr long g = ct_primroot(R);
   constexpr int gG = int(ct_powmod(g, G, R));
   constexpr long ginv = ct_powmod(g, R - 2, R);
@@ -442,12 +474,12 @@ __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P, int ns, const cx<
     int r = gs;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      cx<T> v = act ? Z[(b + r * nbp) * NP + p] : cx<T>{T(0), T(0)};
+      cx<T> v = act ? Z[(b + r * nbp) * ZP + p] : cx<T>{T(0), T(0)};
       if (ns > 1 && act) v = cmul(v, tw[k * (R - 1) + r - 1]);
       x[j] = v;
       r = (r * gG) % R;
     }
-    const cx<T> v0 = act ? Z[b * NP + p] : cx<T>{T(0), T(0)};
+    const cx<T> v0 = act ? Z[b * ZP + p] : cx<T>{T(0), T(0)};
     // forward length-72 DFT of a
     dft_any<T, K>(x);
 #pragma unroll
@@ -488,10 +520,10 @@ __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P, int ns, const cx<
       int oi = gis;
 #pragma unroll
       for (int kk = 0; kk < K; ++kk) {
-        Z[(base + oi * ns) * NP + p] = (NBG > 1) ? out[i][kk] : x[kk];
+        Z[(base + oi * ns) * ZP + p] = (NBG > 1) ? out[i][kk] : x[kk];
         oi = (oi * giG) % R;
       }
-      if (s == 0) Z[base * NP + p] = out0[i];
+      if (s == 0) Z[base * ZP + p] = out0[i];
     }
   }
   __syncthreads();
@@ -536,35 +568,60 @@ __device__ __forceinline__ void dft_engine(cx<T>* Z, int P, int nstages, const S
   }
 }
 
+// Stage list of a kernel specialised for one DFT work length: radices in
+// Stockham order.  StageList<> means the run-time list of the description.
+template <int... Rs>
+struct StageList {
+  static constexpr int count = sizeof...(Rs);
+};
+
+// Compile-time Stockham engine: stage stride NS and twiddle offset TWOFF
+// accumulate as the host builds them (ns * (R - 1) twiddles per stage, the
+// Rader constants first in the constant table).
+template <typename T, int NP, int ZP, int NT, int RADER, int P, int NS, int TWOFF, int R, int... Rest>
+__device__ __forceinline__ void dft_engine_ct(cx<T>* Z, const cx<T>* __restrict__ tw,
+                                              const cx<T>* __restrict__ cs) {
+  if constexpr (R == 73) {
+    static_assert(RADER != 0, "Rader stage needs a Rader kernel shape");
+    stage_rader73<T, NP, NT, P, RADER, P, NS, ZP>(Z, P, NS, tw + TWOFF, cs);
+  } else {
+    stage<T, R, NP, NT, P, P, NS, ZP>(Z, P, NS, tw + TWOFF);
+  }
+  if constexpr (sizeof...(Rest) > 0)
+    dft_engine_ct<T, NP, ZP, NT, RADER, P, NS * R, TWOFF + NS * (R - 1), Rest...>(Z, tw, cs);
+}
+
+template <typename T, int NP, int ZP, int NT, int RADER, int P, int... Rs>
+__device__ __forceinline__ void dft_engine_list(cx<T>* Z, const cx<T>* __restrict__ tw,
+                                                const cx<T>* __restrict__ cs, StageList<Rs...>) {
+  dft_engine_ct<T, NP, ZP, NT, RADER, P, 1, 0, Rs...>(Z, tw, cs);
+}
+
 // Element k of the length-M DFT of pair p after dft_full.
-template <typename T, int NP>
-__device__ __forceinline__ cx<T> dft_result(const cx<T>* Z, const AxisDev& ax, int k, int p) {
-  cx<T> z = Z[k * NP + p];
-  if (ax.bluestein) z = cmul(conj(z), static_cast<const cx<T>*>(ax.chirp)[k]);
+template <typename T, int ZP, class AX>
+__device__ __forceinline__ cx<T> dft_result(const cx<T>* Z, const AX& ax, int k, int p) {
+  cx<T> z = Z[k * ZP + p];
+  if (ax.blue()) z = cmul(conj(z), static_cast<const cx<T>*>(ax.d.chirp)[k]);
   return z;
 }
 
 // ----------------------------------------------------------------------------- tile access
-template <typename T>
-__device__ __forceinline__ T load_elem(const void* p, int64_t i, int f64) {
-  return f64 ? T(static_cast<const double*>(p)[i]) : T(static_cast<const float*>(p)[i]);
-}
 
-// Real tile X: element j of line t of the tile at X[j * TL + t] (lines
-// innermost, for any axis), which is also the packed complex layout
-// Z[m * NP + p] with line t = 2p + w in component w.
-template <int TL>
+// Real tile X: element j of line t of the tile at X[j * XP + t] (lines
+// innermost, for any axis; XP = 2 ZP >= TL), which is also the packed
+// complex layout Z[m * ZP + p] with line t = 2p + w in component w.
+template <int XP>
 __device__ __forceinline__ int xi(int t, int j) {
-  return j * TL + t;
+  return j * XP + t;
 }
 
 // Halfcomplex entry k (complex X_k) of a real DFT stored as h[0..n-1].
-template <typename T, int TL>
+template <typename T, int XP>
 __device__ __forceinline__ cx<T> hc_get(const T* X, int t, int k, int n) {
-  if (k == 0) return {X[xi<TL>(t, 0)], T(0)};
-  if (2 * k < n) return {X[xi<TL>(t, k)], X[xi<TL>(t, n - k)]};
-  if (2 * k == n) return {X[xi<TL>(t, k)], T(0)};
-  return {X[xi<TL>(t, n - k)], -X[xi<TL>(t, k)]};
+  if (k == 0) return {X[xi<XP>(t, 0)], T(0)};
+  if (2 * k < n) return {X[xi<XP>(t, k)], X[xi<XP>(t, n - k)]};
+  if (2 * k == n) return {X[xi<XP>(t, k)], T(0)};
+  return {X[xi<XP>(t, n - k)], -X[xi<XP>(t, k)]};
 }
 
 // DCT-II reorder: v_m = x_{perm(m)} (even indices ascending, then odd descending).
@@ -574,41 +631,41 @@ __device__ __forceinline__ int perm_even_odd(int m, int n) {
 
 // Packing: the complex input of the length-M DFT for pair p at index m
 // (times the chirp for Bluestein, conjugated for inverse kinds).
-template <typename T, int TL, int kind>
-__device__ __forceinline__ cx<T> pack_value(const T* X, const AxisDev& ax, int m, int p) {
-  const int n = ax.n, M = ax.M;
+template <typename T, int XP, int kind, class AX>
+__device__ __forceinline__ cx<T> pack_value(const T* X, const AX& ax, int m, int p) {
+  const int n = ax.n(), M = ax.M();
   const int t0 = 2 * p, t1 = 2 * p + 1;
   cx<T> val = {T(0), T(0)};
   if (m >= M) return val;
   switch (kind) {
     case K_R2HC:
-      val = {X[xi<TL>(t0, m)], X[xi<TL>(t1, m)]};
+      val = {X[xi<XP>(t0, m)], X[xi<XP>(t1, m)]};
       break;
     case K_DCT2:
     case K_DST2: {
       const int j = perm_even_odd(m, n);
-      val = {X[xi<TL>(t0, j)], X[xi<TL>(t1, j)]};
+      val = {X[xi<XP>(t0, j)], X[xi<XP>(t1, j)]};
       if (kind == K_DST2 && (j & 1)) val = {-val.re, -val.im};
       break;
     }
     case K_DCT1: {
       const int j = (m < n) ? m : M - m;
-      val = {X[xi<TL>(t0, j)], X[xi<TL>(t1, j)]};
+      val = {X[xi<XP>(t0, j)], X[xi<XP>(t1, j)]};
       break;
     }
     case K_DST1: {
       if (m == 0 || m == n + 1) break;
       if (m <= n) {
-        val = {X[xi<TL>(t0, m - 1)], X[xi<TL>(t1, m - 1)]};
+        val = {X[xi<XP>(t0, m - 1)], X[xi<XP>(t1, m - 1)]};
       } else {
         const int j = M - m - 1;
-        val = {-X[xi<TL>(t0, j)], -X[xi<TL>(t1, j)]};
+        val = {-X[xi<XP>(t0, j)], -X[xi<XP>(t1, j)]};
       }
       break;
     }
     case K_HC2R: {
-      const cx<T> a = hc_get<T, TL>(X, t0, m, n);
-      const cx<T> b = hc_get<T, TL>(X, t1, m, n);
+      const cx<T> a = hc_get<T, XP>(X, t0, m, n);
+      const cx<T> b = hc_get<T, XP>(X, t1, m, n);
       val = {a.re - b.im, -(a.im + b.re)};  // conj(a + i b)
       break;
     }
@@ -617,14 +674,14 @@ __device__ __forceinline__ cx<T> pack_value(const T* X, const AxisDev& ax, int m
       // V_k = e^{+i pi k/(2n)} (c_k - i c_{n-k}), c_n = 0; DST3 reverses c first.
       const int k = m;
       const int ka = (kind == K_DST3) ? n - 1 - k : k;
-      const T c0k = X[xi<TL>(t0, ka)], c1k = X[xi<TL>(t1, ka)];
+      const T c0k = X[xi<XP>(t0, ka)], c1k = X[xi<XP>(t1, ka)];
       T c0n = T(0), c1n = T(0);
       if (k > 0) {
         const int kb = (kind == K_DST3) ? k - 1 : n - k;
-        c0n = X[xi<TL>(t0, kb)];
-        c1n = X[xi<TL>(t1, kb)];
+        c0n = X[xi<XP>(t0, kb)];
+        c1n = X[xi<XP>(t1, kb)];
       }
-      const cx<T> e = conj(static_cast<const cx<T>*>(ax.pre)[k]);
+      const cx<T> e = conj(static_cast<const cx<T>*>(ax.d.pre)[k]);
       const cx<T> v0 = cmul(e, cx<T>{c0k, -c0n});
       const cx<T> v1 = cmul(e, cx<T>{c1k, -c1n});
       val = {v0.re - v1.im, -(v0.im + v1.re)};  // conj(v0 + i v1)
@@ -633,14 +690,14 @@ __device__ __forceinline__ cx<T> pack_value(const T* X, const AxisDev& ax, int m
     default:
       break;
   }
-  if (ax.bluestein) val = cmul(val, static_cast<const cx<T>*>(ax.chirp)[m]);
+  if (ax.blue()) val = cmul(val, static_cast<const cx<T>*>(ax.d.chirp)[m]);
   return val;
 }
 
 // Unpacking: output coefficient k of line t from the DFT result.
-template <typename T, int NP, int kind>
-__device__ __forceinline__ T unpack_value(const cx<T>* Z, const AxisDev& ax, int t, int k) {
-  const int n = ax.n, M = ax.M;
+template <typename T, int ZP, int kind, class AX>
+__device__ __forceinline__ T unpack_value(const cx<T>* Z, const AX& ax, int t, int k) {
+  const int n = ax.n(), M = ax.M();
   const int p = t >> 1, w = t & 1;
   switch (kind) {
     case K_R2HC:
@@ -649,32 +706,32 @@ __device__ __forceinline__ T unpack_value(const cx<T>* Z, const AxisDev& ax, int
       int kk = k;
       if (kind == K_R2HC && 2 * k > n) kk = n - k;
       if (kind == K_DST2) kk = n - 1 - k;
-      const cx<T> zk = dft_result<T, NP>(Z, ax, kk, p);
-      const cx<T> zr = conj(dft_result<T, NP>(Z, ax, kk == 0 ? 0 : M - kk, p));
+      const cx<T> zk = dft_result<T, ZP>(Z, ax, kk, p);
+      const cx<T> zr = conj(dft_result<T, ZP>(Z, ax, kk == 0 ? 0 : M - kk, p));
       // line 0: (zk + zr)/2 ; line 1: (zk - zr)/(2i)
       cx<T> V;
       if (w == 0) V = {T(0.5) * (zk.re + zr.re), T(0.5) * (zk.im + zr.im)};
       else V = {T(0.5) * (zk.im - zr.im), -T(0.5) * (zk.re - zr.re)};
       if (kind == K_R2HC) return (2 * k <= n) ? V.re : V.im;
-      const cx<T> e = static_cast<const cx<T>*>(ax.pre)[kk];
+      const cx<T> e = static_cast<const cx<T>*>(ax.d.pre)[kk];
       return T(2) * (e.re * V.re - e.im * V.im);
     }
     case K_DCT1: {
-      const cx<T> z = dft_result<T, NP>(Z, ax, k, p);
+      const cx<T> z = dft_result<T, ZP>(Z, ax, k, p);
       return w ? z.im : z.re;
     }
     case K_DST1: {
-      const cx<T> z = dft_result<T, NP>(Z, ax, k + 1, p);
+      const cx<T> z = dft_result<T, ZP>(Z, ax, k + 1, p);
       return w ? z.re : -z.im;
     }
     case K_HC2R: {
-      const cx<T> z = dft_result<T, NP>(Z, ax, k, p);
+      const cx<T> z = dft_result<T, ZP>(Z, ax, k, p);
       return w ? -z.im : z.re;
     }
     case K_DCT3:
     case K_DST3: {
       const int q = (k & 1) ? n - 1 - (k >> 1) : (k >> 1);
-      const cx<T> z = dft_result<T, NP>(Z, ax, q, p);
+      const cx<T> z = dft_result<T, ZP>(Z, ax, q, p);
       T v = w ? -z.im : z.re;
       if (kind == K_DST3 && (k & 1)) v = -v;
       return v;
@@ -685,30 +742,30 @@ __device__ __forceinline__ T unpack_value(const cx<T>* Z, const AxisDev& ax, int
 }
 
 // X (real tile) -> Z (packed complex), through registers.
-template <typename T, int NP, int NT, int PMAX, int kind>
-__device__ __forceinline__ void pack_k(T* X, cx<T>* Z, const AxisDev& ax) {
-  constexpr int TL = 2 * NP;
-  constexpr int E = (PMAX * NP + NT - 1) / NT;
-  const int items = ax.P * NP;
+template <typename T, int NP, int NT, int PMAX, int kind, class AX, int ZP = NP>
+__device__ __forceinline__ void pack_k(T* X, cx<T>* Z, const AX& ax) {
+  constexpr int XP = 2 * ZP;
+  constexpr int E = ((AX::ct ? AX::Pc : PMAX) * NP + NT - 1) / NT;
+  const int items = ax.P() * NP;
   const int tid = opaque_tid();
   cx<T> v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int item = tid + i * NT;
-    if (item < items) v[i] = pack_value<T, TL, kind>(X, ax, item / NP, item % NP);
+    if (item < items) v[i] = pack_value<T, XP, kind>(X, ax, item / NP, item % NP);
   }
   __syncthreads();
   const int tid2 = opaque_tid();
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int item = tid2 + i * NT;
-    if (item < items) Z[item] = v[i];
+    if (item < items) Z[(item / NP) * ZP + item % NP] = v[i];
   }
   __syncthreads();
 }
 
-template <typename T, int NP, int NT, int PMAX>
-__device__ __forceinline__ void pack(T* X, cx<T>* Z, int kind, const AxisDev& ax) {
+template <typename T, int NP, int NT, int PMAX, class AX>
+__device__ __forceinline__ void pack(T* X, cx<T>* Z, int kind, const AX& ax) {
   switch (kind) {
     case K_R2HC: pack_k<T, NP, NT, PMAX, K_R2HC>(X, Z, ax); break;
     case K_HC2R: pack_k<T, NP, NT, PMAX, K_HC2R>(X, Z, ax); break;
@@ -722,13 +779,14 @@ __device__ __forceinline__ void pack(T* X, cx<T>* Z, int kind, const AxisDev& ax
 }
 
 // Z -> X, through registers, optionally dividing by the eigenvalue sum.
-template <typename T, int NP, int NT, int PMAX, int kind>
-__device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const AxisDev& ax, const PassArgs& a,
+template <typename T, int NP, int NT, int PMAX, int kind, class AX, int ZP = NP>
+__device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const AX& ax, const PassArgs& a,
                                          int64_t l0, bool scale) {
   constexpr int TL = 2 * NP;
-  constexpr int E = (2 * PMAX * NP + NT - 1) / NT;
+  constexpr int XP = 2 * ZP;
+  constexpr int E = ((AX::ct ? AX::Nc : PMAX) * TL + NT - 1) / NT;
   static_assert(NT % TL == 0, "thread count must be a multiple of the tile width");
-  const int n = ax.n;
+  const int n = ax.n();
   const int items = n * TL;
   const int tid = opaque_tid();
   const int t = tid % TL;  // fixed per thread
@@ -754,7 +812,7 @@ __device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const AxisDev& ax, cons
     const int item = tid + i * NT;
     if (item < items) {
       const int k = item / TL;
-      T x = unpack_value<T, NP, kind>(Z, ax, t, k);
+      T x = unpack_value<T, ZP, kind>(Z, ax, t, k);
       if (scale) {
         const T lam = lam_other + lt[k];
         x = (dead_line || (zero_line && k == 0)) ? T(0) : x / lam;
@@ -767,13 +825,13 @@ __device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const AxisDev& ax, cons
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int item = tid2 + i * NT;
-    if (item < items) X[xi<TL>(tid2 % TL, item / TL)] = v[i];
+    if (item < items) X[xi<XP>(tid2 % TL, item / TL)] = v[i];
   }
   __syncthreads();
 }
 
-template <typename T, int NP, int NT, int PMAX>
-__device__ __forceinline__ void unpack(cx<T>* Z, T* X, int kind, const AxisDev& ax,
+template <typename T, int NP, int NT, int PMAX, class AX>
+__device__ __forceinline__ void unpack(cx<T>* Z, T* X, int kind, const AX& ax,
                                        const PassArgs& a, int64_t l0, bool scale) {
   switch (kind) {
     case K_R2HC: unpack_k<T, NP, NT, PMAX, K_R2HC>(Z, X, ax, a, l0, scale); break;
@@ -792,12 +850,12 @@ __device__ __forceinline__ void unpack(cx<T>* Z, T* X, int kind, const AxisDev& 
 // Z[m * NP + p] (line t = 2p + w in component w) are the same memory.  A
 // DCT-I input then only needs its even extension, rows m = n..M-1 copied from
 // rows M - m, and a DCT-I output is already in place.
-template <typename T, int NP, int NT>
+template <typename T, int NP, int NT, int ZP = NP>
 __device__ __forceinline__ void dct1_mirror(cx<T>* Z, int n, int M) {
   const int items = (M - n) * NP;
   for (int it = int(threadIdx.x); it < items; it += NT) {
     const int m = n + it / NP, p = it % NP;
-    Z[m * NP + p] = Z[(M - m) * NP + p];
+    Z[m * ZP + p] = Z[(M - m) * ZP + p];
   }
   __syncthreads();
 }
@@ -805,11 +863,12 @@ __device__ __forceinline__ void dct1_mirror(cx<T>* Z, int n, int M) {
 // In-place division of a DCT-I result by the eigenvalue sums, written to the
 // mirrored rows as well, so that the result is at once the input of the
 // inverse DCT-I.
-template <typename T, int NP, int NT>
-__device__ __forceinline__ void dct1_scale_mirror(T* X, const AxisDev& ax, const PassArgs& a, int64_t l0) {
+template <typename T, int NP, int NT, class AX, int ZP = NP>
+__device__ __forceinline__ void dct1_scale_mirror(T* X, const AX& ax, const PassArgs& a, int64_t l0) {
   constexpr int TL = 2 * NP;
+  constexpr int XP = 2 * ZP;
   static_assert(NT % TL == 0, "thread count must be a multiple of the tile width");
-  const int n = ax.n, M = ax.M;
+  const int n = ax.n(), M = ax.M();
   const int tid = int(threadIdx.x);
   const int t = tid % TL;
   const int64_t l = l0 + t;
@@ -825,9 +884,10 @@ __device__ __forceinline__ void dct1_scale_mirror(T* X, const AxisDev& ax, const
   const bool zero_line = a.singular && (l == 0);
   for (int it = tid; it < n * TL; it += NT) {
     const int k = it / TL;
-    const T x = (dead_line || (zero_line && k == 0)) ? T(0) : X[it] / (lam_other + lt[k]);
-    X[it] = x;
-    if (k >= 1 && k <= n - 2) X[(M - k) * TL + t] = x;
+    const int xi_k = k * XP + t;
+    const T x = (dead_line || (zero_line && k == 0)) ? T(0) : X[xi_k] / (lam_other + lt[k]);
+    X[xi_k] = x;
+    if (k >= 1 && k <= n - 2) X[(M - k) * XP + t] = x;
   }
   __syncthreads();
 }
@@ -843,121 +903,229 @@ __device__ __forceinline__ int64_t xcd_tile(unsigned b, unsigned G) {
   return int64_t(x) * q + (x < r ? x : r) + i;
 }
 
-template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
+// One transform phase of a sweep (forward, or the inverse after the
+// eigenvalue division): pack, DFT (or Bluestein convolution), unpack.  K is
+// the compile-time kind of a specialised kernel, or -2 for the run-time kind.
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM, class AX, class ST, int K, int ZP>
+__device__ __forceinline__ void transform_phase(T* X, cx<T>* Z, const AX& ax, const PassArgs& a, int64_t l0,
+                                                int kind_rt, bool scale, int kind_next, bool& mirrored) {
+  const int kind = K >= 0 ? K : kind_rt;
+  const cx<T>* tw = static_cast<const cx<T>*>(ax.d.tw);
+  const cx<T>* cs = static_cast<const cx<T>*>(ax.d.cs);
+  // without a chirp convolution the in-place shortcuts apply
+  const bool inplace = !ax.blue();
+  if (inplace && kind == K_DCT1) {
+    if (!mirrored) dct1_mirror<T, NP, NT, ZP>(Z, ax.n(), ax.M());
+  } else if (!(inplace && kind == K_R2HC)) {
+    if constexpr (K >= 0) pack_k<T, NP, NT, PMAX, K, AX, ZP>(X, Z, ax);
+    else pack<T, NP, NT, PMAX>(X, Z, kind, ax);
+  }
+  // Stockham DFT; for Bluestein: DFT, times the kernel spectrum, conjugate, DFT
+  // (the unpacker conjugates and applies the chirp).  The two DFTs share one
+  // copy of the engine code (run-time loop).
+  const int nrep = ax.blue() ? 2 : 1;
+  for (int rep = 0; rep < nrep; ++rep) {
+    if (rep == 1) {
+      const cx<T>* bh = static_cast<const cx<T>*>(ax.d.bhat);
+      const int items = ax.P() * NP;
+      for (int item = threadIdx.x; item < items; item += NT) {
+        const int zi = (item / NP) * ZP + item % NP;
+        Z[zi] = conj(cmul(Z[zi], bh[item / NP]));
+      }
+      __syncthreads();
+    }
+    if constexpr (ST::count > 0) dft_engine_list<T, NP, ZP, NT, RADER, AX::Pc>(Z, tw, cs, ST{});
+    else dft_engine<T, NP, NT, PMAX, RADER, SLIM>(Z, ax.P(), ax.d.nstages, ax.d.st, tw, cs);
+  }
+  if (inplace && kind == K_DCT1) {
+    if (scale) {
+      dct1_scale_mirror<T, NP, NT, AX, ZP>(X, ax, a, l0);
+      mirrored = kind_next == K_DCT1;
+    }
+  } else {
+    if constexpr (K >= 0) unpack_k<T, NP, NT, PMAX, K, AX, ZP>(Z, X, ax, a, l0, scale);
+    else unpack<T, NP, NT, PMAX>(Z, X, kind, ax, a, l0, scale);
+  }
+}
+
+
+// One sweep over tile `tile`.  AX, KF, KB, ST: length view, forward and
+// inverse kinds (-1: no inverse) and stage list of a kernel specialised for
+// one transform (Ax<>, -2, -2, StageList<>: everything from the description).
+// ZP: LDS row pitch in complex values (NP for the generic shapes).
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM, class AX = Ax<>, int KF = -2, int KB = -2,
+          class ST = StageList<>, int ZP = NP>
 __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, unsigned char* smem) {
+  static_assert(ZP == NP || (KF >= 0 && ST::count > 0 && AX::ct), "a padded pitch needs a specialised kernel");
   constexpr int TL = 2 * NP;
+  constexpr int XP = 2 * ZP;
   T* X = reinterpret_cast<T*>(smem);
   cx<T>* Z = reinterpret_cast<cx<T>*>(smem);
-  const AxisDev& ax = a.ax;
-  const int n = ax.n;
+  const AX ax{a.ax};
+  const int n = ax.n();
   const int64_t B = a.inner;
   const int64_t l0 = tile * TL;
 
-  // ---- load.  Thread (t, j0) reads elements j0, j0 + NT/TL, ... of line t:
-  // lines are innermost in LDS (conflict-free writes), and the TL lines of a
-  // contiguous axis are read TL at a time, their cache lines being reused by
-  // the following requests.  Elements are requested in chunks of CH per
-  // thread, all CH before any LDS write.
-  constexpr int ELD = (2 * NP * PMAX + NT - 1) / NT;  // bound for n <= PMAX
+  // Tile I/O of a specialised kernel (compile-time n) whose tile lies in one
+  // plane of the array (B % TL == 0, or B == 1: the contiguous axis) and whose
+  // byte offsets fit 32 bits: every element of the thread is requested before
+  // the first LDS write, from a uniform tile base pointer and 32-bit lane
+  // offsets.  Contiguous axis: the TL lines are TL * n consecutive elements,
+  // read by consecutive lanes (fully coalesced) and transposed into LDS
+  // through the padded pitch.  Strided axes: lanes take TL adjacent lines of
+  // one row (TL consecutive elements), rows NT / TL apart per request.
+  constexpr bool kFast = AX::ct && (TL * AX::Nc) % NT == 0;
+  constexpr int EF = kFast ? TL * AX::Nc / NT : 1;  // elements per thread
+  int mode = 0;       // 0 generic, 1 contiguous fast path, 2 strided fast path
+  int64_t tbase = 0;  // element offset of the tile's first element
+  if constexpr (kFast) {
+    const bool full = l0 + TL <= a.nlines;
+    constexpr int64_t kLim = int64_t(1) << 29;  // elements: byte offsets of 8-byte values stay below 2^32
+    if (B == 1) {
+      mode = (full && int64_t(TL) * n < kLim) ? 1 : 0;
+      tbase = l0 * n;
+    } else {
+      mode = (full && B % TL == 0 && int64_t(n) * B < kLim) ? 2 : 0;
+      tbase = (l0 / B) * (int64_t(n) * B) + (l0 % B);
+    }
+  }
+  const uint32_t Bu = uint32_t(B);
+  // element e of this thread: 32-bit element offset from the tile base and LDS index
+  auto off_c = [&](int tid, int e) { return uint32_t(tid + e * NT); };
+  auto xi_c = [&](int tid, int e) {
+    const int q = tid + e * NT;
+    return (q % (AX::ct ? AX::Nc : 1)) * XP + q / (AX::ct ? AX::Nc : 1);
+  };
+  auto off_s = [&](int tid, int e) { return uint32_t(tid / TL + e * (NT / TL)) * Bu + uint32_t(tid % TL); };
+  auto xi_s = [&](int tid, int e) { return (tid / TL + e * (NT / TL)) * XP + tid % TL; };
+
+  // ---- load.  Generic path: thread (t, j0) reads elements j0, j0 + NT/TL,
+  // ... of line t (lines innermost in LDS, conflict-free writes), CH at a
+  // time, all CH before any LDS write; elements outside the array are read
+  // from its first element and replaced by zeros, so no request is
+  // predicated.  The element type of the source is a uniform branch around
+  // whole loops.
+  constexpr int ELD = (2 * NP * (AX::ct ? AX::Nc : PMAX) + NT - 1) / NT;  // bound for n <= PMAX
   constexpr int CH = ELD < 16 ? ELD : 16;
-  {
+  auto fast_load = [&](auto src_elem, auto off, auto xi) {
+    using S = decltype(src_elem);
     const int tid = opaque_tid();
-    {
-      const int t = tid % TL;
-      const int64_t l = l0 + t;
-      const bool ok = l < a.nlines;
-      const int64_t base = ok ? (l / B) * (int64_t(n) * B) + (l % B) : 0;
-      for (int c = 0; c < ELD && c * (NT / TL) < n; c += CH) {
-        T ld[CH];
+    const char* sb = reinterpret_cast<const char*>(static_cast<const S*>(a.src) + tbase);
+    S ld[EF];
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-          const int j = tid / TL + (c + i) * (NT / TL);
-          ld[i] = (ok && j < n) ? load_elem<T>(a.src, base + int64_t(j) * B, a.src_f64) : T(0);
-        }
+    for (int e = 0; e < EF; ++e) ld[e] = *reinterpret_cast<const S*>(sb + off(tid, e) * uint32_t(sizeof(S)));
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-          const int j = tid / TL + (c + i) * (NT / TL);
-          if (j < n) X[j * TL + t] = ld[i];
-        }
+    for (int e = 0; e < EF; ++e) X[xi(tid, e)] = T(ld[e]);
+  };
+  auto generic_load = [&](auto src_elem) {
+    using S = decltype(src_elem);
+    const S* src = static_cast<const S*>(a.src);
+    const int tid = opaque_tid();
+    const int t = tid % TL;
+    const int64_t l = l0 + t;
+    const bool ok = l < a.nlines;
+    const int64_t base = ok ? (l / B) * (int64_t(n) * B) + (l % B) : 0;
+    for (int c = 0; c < ELD && c * (NT / TL) < n; c += CH) {
+      S ld[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int j = tid / TL + (c + i) * (NT / TL);
+        ld[i] = src[(ok && j < n) ? base + int64_t(j) * B : 0];
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int j = tid / TL + (c + i) * (NT / TL);
+        if (j < n) X[j * XP + t] = ok ? T(ld[i]) : T(0);
       }
     }
+  };
+  if (mode == 1) {
+    if (a.src_f64) fast_load(double(0), off_c, xi_c);
+    else fast_load(float(0), off_c, xi_c);
+  } else if (mode == 2) {
+    if (a.src_f64) fast_load(double(0), off_s, xi_s);
+    else fast_load(float(0), off_s, xi_s);
+  } else {
+    if (a.src_f64) generic_load(double(0));
+    else generic_load(float(0));
   }
   __syncthreads();
 
   // ---- forward transform, and optionally eigenvalue division + inverse transform.
-  // The phases and the two DFTs of a Bluestein convolution share one copy of
-  // the DFT engine code (runtime loops, not unrolled).
-  const cx<T>* tw = static_cast<const cx<T>*>(ax.tw);
-  const cx<T>* cs = static_cast<const cx<T>*>(ax.cs);
-  const cx<T>* bh = static_cast<const cx<T>*>(ax.bhat);
-  const int nphase = a.kind_b >= 0 ? 2 : 1;
-  const int nrep = ax.bluestein ? 2 : 1;
-  // without a chirp convolution the in-place shortcuts apply
-  const bool inplace = !ax.bluestein;
   bool mirrored = false;  // the middle step already built the DCT-I input
-  for (int phase = 0; phase < nphase; ++phase) {
-    const int kind = phase == 0 ? a.kind_f : a.kind_b;
-    if (inplace && kind == K_DCT1) {
-      if (!mirrored) dct1_mirror<T, NP, NT>(Z, n, ax.M);
-    } else if (!(inplace && kind == K_R2HC)) {
-      pack<T, NP, NT, PMAX>(X, Z, kind, ax);
-    }
-    // Stockham DFT; for Bluestein: DFT, times the kernel spectrum, conjugate, DFT
-    // (the unpacker conjugates and applies the chirp).
-    for (int rep = 0; rep < nrep; ++rep) {
-      if (rep == 1) {
-        const int items = ax.P * NP;
-        for (int item = threadIdx.x; item < items; item += NT) Z[item] = conj(cmul(Z[item], bh[item / NP]));
-        __syncthreads();
-      }
-      dft_engine<T, NP, NT, PMAX, RADER, SLIM>(Z, ax.P, ax.nstages, ax.st, tw, cs);
-    }
-    const bool scale = phase == 0 && nphase == 2;
-    if (inplace && kind == K_DCT1) {
-      if (scale) {
-        dct1_scale_mirror<T, NP, NT>(X, ax, a, l0);
-        mirrored = a.kind_b == K_DCT1;
-      }
-    } else {
-      unpack<T, NP, NT, PMAX>(Z, X, kind, ax, a, l0, scale);
+  if constexpr (KF >= 0) {
+    transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, KF, ZP>(X, Z, ax, a, l0, KF, KB >= 0, KB, mirrored);
+    if constexpr (KB >= 0)
+      transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, KB, ZP>(X, Z, ax, a, l0, KB, false, -1, mirrored);
+  } else {
+    const int nphase = a.kind_b >= 0 ? 2 : 1;
+    for (int phase = 0; phase < nphase; ++phase) {
+      const int kind = phase == 0 ? a.kind_f : a.kind_b;
+      transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, -2, ZP>(X, Z, ax, a, l0, kind,
+                                                                     phase == 0 && nphase == 2, a.kind_b, mirrored);
     }
   }
 
-  // ---- store (in update mode the old values of a chunk are requested first)
-  {
+  // ---- store (in update mode the old values are requested first)
+  const double shift = (a.update && a.shift) ? a.shift[0] : 0.0;
+  auto fast_store = [&](auto off, auto xi) {
     const int tid = opaque_tid();
-    const double shift = (a.update && a.shift) ? a.shift[0] : 0.0;
-    double* d64 = static_cast<double*>(a.dst);
-    float* d32 = static_cast<float*>(a.dst);
-    {
-      const int t = tid % TL;
-      const int64_t l = l0 + t;
-      if (l < a.nlines) {
-        const int64_t base = (l / B) * (int64_t(n) * B) + (l % B);
-        for (int c = 0; c < ELD && c * (NT / TL) < n; c += CH) {
-          double old[CH];
-          if (a.update) {
+    if (a.update) {
+      char* db = reinterpret_cast<char*>(static_cast<double*>(a.dst) + tbase);
+      double old[EF];
 #pragma unroll
-            for (int i = 0; i < CH; ++i) {
-              const int j = tid / TL + (c + i) * (NT / TL);
-              old[i] = j < n ? d64[base + int64_t(j) * B] : 0.0;
-            }
-          }
+      for (int e = 0; e < EF; ++e) old[e] = *reinterpret_cast<const double*>(db + off(tid, e) * 8u);
 #pragma unroll
-          for (int i = 0; i < CH; ++i) {
-            const int j = tid / TL + (c + i) * (NT / TL);
-            if (j < n) {
-              const T x = X[j * TL + t];
-              const int64_t o = base + int64_t(j) * B;
-              if (a.update) d64[o] = old[i] + double(x) - shift;
-              else if (a.dst_f64) d64[o] = double(x);
-              else d32[o] = float(x);
-            }
-          }
+      for (int e = 0; e < EF; ++e)
+        *reinterpret_cast<double*>(db + off(tid, e) * 8u) = old[e] + double(X[xi(tid, e)]) - shift;
+    } else if (a.dst_f64) {
+      char* db = reinterpret_cast<char*>(static_cast<double*>(a.dst) + tbase);
+#pragma unroll
+      for (int e = 0; e < EF; ++e) *reinterpret_cast<double*>(db + off(tid, e) * 8u) = double(X[xi(tid, e)]);
+    } else {
+      char* db = reinterpret_cast<char*>(static_cast<float*>(a.dst) + tbase);
+#pragma unroll
+      for (int e = 0; e < EF; ++e) *reinterpret_cast<float*>(db + off(tid, e) * 4u) = float(X[xi(tid, e)]);
+    }
+  };
+  if (mode == 1) {
+    fast_store(off_c, xi_c);
+    return;
+  }
+  if (mode == 2) {
+    fast_store(off_s, xi_s);
+    return;
+  }
+  auto generic_store = [&](auto dst_elem, bool update) {
+    using D = decltype(dst_elem);
+    const int tid = opaque_tid();
+    D* dst = static_cast<D*>(a.dst);
+    const int t = tid % TL;
+    const int64_t l = l0 + t;
+    if (l >= a.nlines) return;
+    const int64_t base = (l / B) * (int64_t(n) * B) + (l % B);
+    for (int c = 0; c < ELD && c * (NT / TL) < n; c += CH) {
+      D old[CH];
+      if (update) {
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int j = tid / TL + (c + i) * (NT / TL);
+          old[i] = dst[j < n ? base + int64_t(j) * B : base];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int j = tid / TL + (c + i) * (NT / TL);
+        if (j < n) {
+          const T x = X[j * XP + t];
+          dst[base + int64_t(j) * B] = update ? D(double(old[i]) + double(x) - shift) : D(x);
         }
       }
     }
-  }
+  };
+  if (a.update) generic_store(double(0), true);
+  else if (a.dst_f64) generic_store(double(0), false);
+  else generic_store(float(0), false);
 }
 
 
@@ -1009,6 +1177,45 @@ template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
 hipError_t launch_lp_batch(const BatchPassArgs& b, int blocks, hipStream_t s, size_t lds) {
   hipLaunchKernelGGL((line_pass_batch<T, NP, NT, PMAX, RADER, SLIM>), dim3(unsigned(blocks)), dim3(NT), lds, s, b);
   return hipGetLastError();
+}
+
+// LDS row pitch (complex values) of the specialised kernels: one complex
+// value of padding per row, so that rows written by consecutive lanes of the
+// contiguous-axis load start on different banks.
+template <typename T, int NP>
+constexpr int spec_pitch() {
+  return NP + 1;
+}
+
+// A kernel specialised for one transform: line length N, DFT length M, work
+// length P, kinds KF / KB (KB = -1: no inverse) and the Stockham stage list,
+// all compile-time; everything else (arrays, strides, tables, eigenvalues)
+// comes from the pass description as in line_pass.
+template <typename T, int NP, int NT, int RADER, int SLIM, int N, int M, int P, int KF, int KB, int... Rs>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM, RADER>::v, 8)))
+line_pass_spec(PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  line_pass_body<T, NP, NT, P, RADER, SLIM, Ax<N, M, P>, KF, KB, StageList<Rs...>, spec_pitch<T, NP>()>(
+      a, xcd_tile(blockIdx.x, gridDim.x), smem);
+}
+
+template <typename T, int NP, int NT, int RADER, int SLIM, int N, int M, int P, int KF, int KB, int... Rs>
+hipError_t launch_spec_t(const PassArgs& a, hipStream_t s, size_t lds) {
+  constexpr int64_t TL = 2 * NP;
+  if (a.ax.n != N || a.ax.M != M || a.ax.P != P || a.kind_f != KF || a.kind_b != KB ||
+      a.ax.nstages != int(sizeof...(Rs)))
+    return hipErrorInvalidValue;  // the description must be the one this kernel was compiled for
+  const int64_t blocks = (a.nlines + TL - 1) / TL;
+  hipLaunchKernelGGL((line_pass_spec<T, NP, NT, RADER, SLIM, N, M, P, KF, KB, Rs...>), dim3(unsigned(blocks)),
+                     dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int NP, int NT, int RADER, int SLIM, int N, int M, int P, int KF, int KB, int... Rs>
+hipError_t prepare_spec_t() {
+  return hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&line_pass_spec<T, NP, NT, RADER, SLIM, N, M, P, KF, KB, Rs...>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>

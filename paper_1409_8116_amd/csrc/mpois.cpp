@@ -27,6 +27,11 @@ void kernel_cfg(int i, int* f64, int* np, int* nt, int* pmax);
 int kernel_cfg_rader(int i);
 int kernel_cfg_slim(int i);
 size_t line_pass_lds(int cfg, int n, int P);
+int num_specs();
+int find_spec(bool f64, int n, int M, int P, int kind_f, int kind_b, const std::vector<int>& radices);
+void spec_shape(int i, int* f64, int* np, int* nt, int* n);
+size_t spec_lds(int i);
+hipError_t launch_spec(int i, const PassArgs& a, hipStream_t s);
 hipError_t prepare_kernels();
 hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s);
 int resid_blocks(const int64_t n[3]);
@@ -292,9 +297,14 @@ void to_prec(const std::vector<std::complex<double>>& src, std::vector<T>* dst) 
 // ---------------------------------------------------------------------------- plan
 struct Pass {
   PassArgs args{};
-  int cfg = 0;
+  int cfg = 0;    // generic kernel shape (cfgs.h); batches always use it
+  int spec = -1;  // specialised kernel (specs.h) used by single-grid executes, or -1
   int axis = 0;   // axis this pass transforms
 };
+
+// Kernel ids reported by mpois_profile: generic shapes 0.., residual 100,
+// reduction 101, specialised kernels kSpecBase + spec index.
+constexpr int kSpecBase = 200;
 
 struct SubPlan {
   int ndim = 0;
@@ -792,6 +802,14 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
       p.cfg = default_cfg(pl->f64work, int(n), int(shape.P), has_rader(shape), has_odd_large(shape));
     }
     a.ax = pl->tables[ti].dev;
+    // a kernel compiled for exactly this transform, unless switched off
+    // (MPOIS_NO_SPEC=1, a test hook comparing it with the generic shapes)
+    const char* nospec = std::getenv("MPOIS_NO_SPEC");
+    if (!(nospec && nospec[0] == '1')) {
+      const AxisShape& sh = pl->tables[ti].shape;
+      p.spec = find_spec(pl->f64work, int(n), int(sh.M), int(sh.P), a.kind_f, a.kind_b, sh.radices);
+      if (p.spec >= 0 && spec_lds(p.spec) > size_t(kMaxLds)) p.spec = -1;
+    }
     return p;
   };
   for (int d = D - 1; d >= 1 && st == MPOIS_OK; --d) sp->passes.push_back(axis_pass(d, false, false));
@@ -924,10 +942,10 @@ hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, 
     a.dst_f64 = last ? out_f64 : work_f64;
     a.update = (last && update) ? 1 : 0;
     a.shift = shift;
-    hipError_t e = launch_line_pass(p.cfg, a, s);
+    hipError_t e = p.spec >= 0 ? launch_spec(p.spec, a, s) : launch_line_pass(p.cfg, a, s);
     if (e != hipSuccess) return e;
     const double pts = double(sp.npts);
-    prof_mark(pl, p.cfg, pts * ((a.src_f64 ? 8 : 4) + (a.dst_f64 ? 8 : 4) + (a.update ? 8 : 0)), s);
+    prof_mark(pl, p.spec >= 0 ? kSpecBase + p.spec : p.cfg, pts * ((a.src_f64 ? 8 : 4) + (a.dst_f64 ? 8 : 4) + (a.update ? 8 : 0)), s);
   }
   return hipSuccess;
 }
@@ -1443,6 +1461,15 @@ mpois_status mpois_destroy(mpois_plan pl) {
 size_t mpois_workspace_bytes(mpois_plan pl) { return pl ? pl->bytes : 0; }
 
 mpois_status mpois_kernel_shape(int cfg, int* elem_bytes, int* pairs, int* threads, int* max_len) {
+  if (cfg >= kSpecBase && cfg < kSpecBase + num_specs()) {
+    int f64, np, nt, n;
+    spec_shape(cfg - kSpecBase, &f64, &np, &nt, &n);
+    if (elem_bytes) *elem_bytes = f64 ? 8 : 4;
+    if (pairs) *pairs = np;
+    if (threads) *threads = nt;
+    if (max_len) *max_len = n;
+    return MPOIS_OK;
+  }
   if (cfg < 0 || cfg >= num_kernel_cfgs()) return MPOIS_ERR_INVALID;
   int f64, np, nt, pmax;
   kernel_cfg(cfg, &f64, &np, &nt, &pmax);

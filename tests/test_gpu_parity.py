@@ -338,3 +338,32 @@ def test_every_tuner_radix_plan_matches_oracle(variant, monkeypatch):
             print(f"[tuner variant {variant}] {shape} {kinds} {prec}", flush=True)
             out, _ = gpu_solve(g, shape, h, bc, grid, "fd", prec, tune=True)
             assert rel_err(out, ref) <= TOL[prec], (variant, shape, kinds, prec)
+
+
+# ------------------------------------------------------------------ kernels specialised for one transform
+SPEC_CASES = [
+    ((512, 6, 512), ("N", "N", "N"), ("v", "v", "v")),      # 512-point DCT-I: forward and fused
+    ((256, 4, 256), ("P", "D", "N"), ("v", "s", "s")),      # 256: DCT-II/III, fused real DFT
+    ((4, 256, 256), ("P", "D", "N"), ("v", "s", "s")),      # 256: DST-II/III
+    ((1024, 4, 256), ("P", "N", "P"), ("v", "s", "v")),     # 1024 fused real DFT, 256 real DFT
+    ((4, 512, 256), ("P", "N", "P"), ("v", "s", "v")),      # 512: DCT-II/III
+    ((32, 32, 32), ("P", "P", "P"), ("v", "v", "v")),       # 32-point real DFT
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32r"])
+def test_specialised_kernels_match_generic_and_oracle(prec, monkeypatch):
+    """Plans that use the kernels compiled for one transform against plans
+    forced onto the generic shapes (MPOIS_NO_SPEC=1), and both against the oracle."""
+    for shape, bc, grid in SPEC_CASES:
+        h = tuple(1.0 / n for n in shape)
+        g = np.random.default_rng(17).standard_normal(shape)
+        print(f"[spec] {prec} {shape} {bc} {grid}", flush=True)
+        monkeypatch.delenv("MPOIS_NO_SPEC", raising=False)
+        out_s, _ = gpu_solve(g, shape, h, bc, grid, "fd", prec)
+        monkeypatch.setenv("MPOIS_NO_SPEC", "1")
+        out_g, _ = gpu_solve(g, shape, h, bc, grid, "fd", prec)
+        monkeypatch.delenv("MPOIS_NO_SPEC")
+        assert rel_err(out_s, out_g) <= (1e-5 if prec == "f32" else 1e-13), (shape, prec)
+        ref = oracle_solve(g, shape, h, bc, grid, "fd")
+        assert rel_err(out_s, ref) <= TOL[prec], (shape, prec)
