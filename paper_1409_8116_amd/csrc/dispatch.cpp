@@ -121,14 +121,20 @@ void spec_shape(int i, int* f64, int* np, int* nt, int* n) {
 }
 
 // LDS of a specialised kernel: rows of ZP = NP + 1 complex values (the
-// padded pitch of spec_pitch in line_pass.h), n real rows or P complex rows.
+// padded pitch of spec_pitch in line_pass.h), n real rows or P complex rows,
+// as spec_main_lds in line_pass.h computes it.
 size_t spec_lds(int i) {
   const SpecInfo& c = kSpecs[i];
   const size_t es = c.f64 ? 8 : 4;
   const size_t zp = size_t(c.np) + 1;
   const size_t xs = 2 * zp * size_t(c.n);
   const size_t zs = 2 * zp * size_t(c.P);
-  return (xs > zs ? xs : zs) * es;
+  const size_t main = ((xs > zs ? xs : zs) * es + 15) / 16 * 16;
+  // fused kernels stage the axis's eigenvalues behind the tile when that
+  // keeps two workgroups per CU (spec_stage_lam in line_pass.h)
+  const size_t half = 80 * 1024, lam = size_t(c.n) * es;
+  const bool stage = c.kb >= 0 && (main + lam <= half || main > half);
+  return main + (stage ? lam : 0);
 }
 
 hipError_t launch_spec(int i, const PassArgs& a, hipStream_t s) {

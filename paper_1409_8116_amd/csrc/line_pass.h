@@ -18,6 +18,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+
 #include "internal.h"
 
 namespace mpois {
@@ -42,6 +43,28 @@ __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
 // multiply by -i
 template <typename T>
 __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.im, -a.re}; }
+// c ? a : b per component (a conditional on the struct itself would select
+// between addresses and keep the operands in scratch memory)
+template <typename T>
+__device__ __forceinline__ cx<T> csel(bool c, cx<T> a, cx<T> b) { return {c ? a.re : b.re, c ? a.im : b.im}; }
+
+// x / d from the hardware reciprocal and Newton steps (two in FP64, one in
+// FP32) and a final correction of the quotient: within an ulp or so of the
+// rounded quotient, at a fraction of the cost of IEEE division.  Used by the
+// specialised kernels for the eigenvalue division.
+__device__ __forceinline__ float quick_div(float x, float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  r = __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
+  const float q = x * r;
+  return __builtin_fmaf(__builtin_fmaf(-d, q, x), r, q);
+}
+__device__ __forceinline__ double quick_div(double x, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  const double q = x * r;
+  return __builtin_fma(__builtin_fma(-d, q, x), r, q);
+}
 
 // Length view of one axis transform.  Ax<> reads the line length n, the
 // complex DFT length M and the work length P (P > M: Bluestein) from the
@@ -282,6 +305,38 @@ __device__ __forceinline__ void dft_2level(cx<T>* v) {
   }
 }
 
+// Prime-factor (Good-Thomas) codelet for coprime R1, R2: input n = (R2 n1 +
+// R1 n2) mod R, DFT-R1 over n1, DFT-R2 over n2, output k with k = k1 mod R1
+// and k = k2 mod R2 (Chinese remainder map); no twiddle factors.
+constexpr int ct_modinv(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
+template <typename T, int R1, int R2>
+__device__ __forceinline__ void dft_pfa(cx<T>* v) {
+  constexpr int R = R1 * R2;
+  constexpr int e1 = R2 * ct_modinv(R2 % R1, R1);  // = 1 mod R1, 0 mod R2
+  constexpr int e2 = R1 * ct_modinv(R1 % R2, R2);  // = 0 mod R1, 1 mod R2
+  cx<T> t[R2][R1];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) t[n2][n1] = v[(R2 * n1 + R1 * n2) % R];
+    dft_any<T, R1>(t[n2]);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cx<T> u[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) u[n2] = t[n2][k1];
+    dft_any<T, R2>(u);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[(e1 * k1 + e2 * k2) % R] = u[k2];
+  }
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void dft_any(cx<T>* v) {
   if constexpr (R == 1) return;
@@ -290,13 +345,13 @@ __device__ __forceinline__ void dft_any(cx<T>* v) {
   else if constexpr (R == 4) dft4(v);
   else if constexpr (R == 8) dft8(v);
   else if constexpr (R == 9) dft_2level<T, 3, 3>(v);
-  else if constexpr (R == 14) dft_2level<T, 7, 2>(v);
+  else if constexpr (R == 14) dft_pfa<T, 7, 2>(v);
   else if constexpr (R == 16) dft_2level<T, 4, 4>(v);
-  else if constexpr (R == 18) dft_2level<T, 2, 9>(v);
-  else if constexpr (R == 36) dft_2level<T, 4, 9>(v);
+  else if constexpr (R == 18) dft_pfa<T, 2, 9>(v);
+  else if constexpr (R == 36) dft_pfa<T, 4, 9>(v);
   else if constexpr (R == 32) dft_2level<T, 8, 4>(v);
   else if constexpr (R == 64) dft_2level<T, 8, 8>(v);
-  else if constexpr (R == 72) dft_2level<T, 8, 9>(v);
+  else if constexpr (R == 72) dft_pfa<T, 8, 9>(v);
   else dft_odd<T, R>(v);
 }
 
@@ -405,10 +460,10 @@ __device__ __forceinline__ void lane_radix2(cx<T>* x, int s) {
     const cx<T> xp = lane_xor_cx<H>(x[k]);
     if constexpr (!DIT) {
       const cx<T> t = {xp.re + sg * x[k].re, xp.im + sg * x[k].im};
-      x[k] = (H == 1) ? t : cmul(t, top ? cx<T>{T(1), T(0)} : w);
+      x[k] = (H == 1) ? t : cmul(t, csel(top, cx<T>{T(1), T(0)}, w));
     } else {
       // top: x + w x' ; bottom: x' - w x  ==  u + sg * (w v) with (u, v) = top ? (x, x') : (x', x)
-      const cx<T> u = top ? x[k] : xp, v = top ? xp : x[k];
+      const cx<T> u = csel(top, x[k], xp), v = csel(top, xp, x[k]);
       const cx<T> wv = (H == 1) ? v : cmul(w, v);
       x[k] = {u.re + sg * wv.re, u.im + sg * wv.im};
     }
@@ -436,6 +491,66 @@ __device__ __forceinline__ int lane_bitrev(int s) {
 // two.  tab holds dhat (72 values, DFT_72(d)/72) then e^{-2 pi i j/72}, j < 72.
 // Every lane of a round runs the arithmetic (idle groups on zeros) so each
 // lane move has its partner; rounds with no work at all are skipped.
+// Rader permutation of the prime 73 for G lanes per butterfly, built by the
+// compiler: lane s gathers inputs g^(s + G j) and scatters outputs to
+// g^-(s + G kk), j, kk < 72 / G.
+template <int G>
+struct RaderIdx {
+  int in[G][72 / G];
+  int out[G][72 / G];
+  constexpr RaderIdx() : in(), out() {
+    const long g = ct_primroot(73), ginv = ct_powmod(g, 71, 73);
+    for (int s = 0; s < G; ++s)
+      for (int j = 0; j < 72 / G; ++j) {
+        in[s][j] = int(ct_powmod(g, s + G * j, 73));
+        out[s][j] = int(ct_powmod(ginv, s + G * j, 73));
+      }
+  }
+};
+template <int G>
+struct RaderTab {
+  static constexpr RaderIdx<G> t{};
+};
+
+// Entry J of row s of a Rader table for lane group index s < G (2 or 4): a
+// blend of the row's compile-time entries by the bits of s.
+template <int G, bool OUT, int J>
+__device__ __forceinline__ int lane_entry(int s) {
+  constexpr auto& t = OUT ? RaderTab<G>::t.out : RaderTab<G>::t.in;
+  if constexpr (G == 2) {
+    constexpr int a = t[0][J], d = t[1][J] - t[0][J];
+    return a + s * d;
+  } else {
+    static_assert(G == 4, "two or four lanes");
+    constexpr int a = t[0][J], d1 = t[1][J] - t[0][J], d2 = t[2][J] - t[0][J];
+    constexpr int d3 = t[3][J] - t[2][J] - t[1][J] + t[0][J];
+    const int b0 = s & 1, b1 = s >> 1;
+    return a + b0 * d1 + b1 * d2 + (b0 & b1) * d3;
+  }
+}
+
+// Gather of Rader inputs J.. of lane group s (compile-time recursion, so the
+// permutation entries are constant expressions), with the stage twiddles
+// when ns > 1.
+template <typename T, int G, int K, int J, int ZP>
+__device__ __forceinline__ void rader_gather(cx<T>* x, const cx<T>* Z, int b, int nbp, int p, int s, int ns, int k,
+                                             const cx<T>* __restrict__ tw, bool act) {
+  const int r = lane_entry<G, false, J>(s);
+  cx<T> v = Z[(b + r * nbp) * ZP + p];
+  if (ns > 1) v = cmul(v, tw[k * 72 + r - 1]);
+  x[J].re = act ? v.re : T(0);
+  x[J].im = act ? v.im : T(0);
+  if constexpr (J + 1 < K) rader_gather<T, G, K, J + 1, ZP>(x, Z, b, nbp, p, s, ns, k, tw, act);
+}
+
+// Scatter of Rader outputs KK.. of lane group s to rows base + ns g^-(s + G kk).
+template <typename T, int G, int K, int KK, int ZP>
+__device__ __forceinline__ void rader_scatter(cx<T>* Z, const cx<T>* x, int base, int ns, int p, int s) {
+  const int oi = lane_entry<G, true, KK>(s);
+  Z[(base + oi * ns) * ZP + p] = x[KK];
+  if constexpr (KK + 1 < K) rader_scatter<T, G, K, KK + 1, ZP>(Z, x, base, ns, p, s);
+}
+
 template <typename T, int NP, int NT, int PMAX, int G, int PC = 0, int NSC = 0, int ZP = NP>
 __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P_rt, int ns_rt, const cx<T>* __restrict__ tw,
                                               const cx<T>* __restrict__ tab) {
@@ -471,19 +586,37 @@ __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P_rt, int ns_rt, con
     const int p = act ? item % NP : 0;
     const int b = act ? item / NP : 0;
     const int k = b % ns;
-    int r = gs;
+    // idle groups (b = p = 0) read valid entries and discard the results:
+    // no request is predicated
+    if constexpr (G <= 4) {
+      rader_gather<T, G, K, 0, ZP>(x, Z, b, nbp, p, s, ns, k, tw, act);
+    } else {
+      int r = gs;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      cx<T> v = act ? Z[(b + r * nbp) * ZP + p] : cx<T>{T(0), T(0)};
-      if (ns > 1 && act) v = cmul(v, tw[k * (R - 1) + r - 1]);
-      x[j] = v;
-      r = (r * gG) % R;
+      for (int j = 0; j < K; ++j) {
+        cx<T> v = Z[(b + r * nbp) * ZP + p];
+        if (ns > 1) v = cmul(v, tw[k * (R - 1) + r - 1]);
+        x[j] = v;
+        r = (r * gG) % R;
+      }
     }
-    const cx<T> v0 = act ? Z[b * ZP + p] : cx<T>{T(0), T(0)};
+    cx<T> v0 = Z[b * ZP + p];
+    v0.re = act ? v0.re : T(0);
+    v0.im = act ? v0.im : T(0);
     // forward length-72 DFT of a
     dft_any<T, K>(x);
+    // twiddles e^{-2 pi i s k1 / 72}: compile-time constants for two lanes
+    // (identity on lane 0), a table otherwise
 #pragma unroll
-    for (int k1 = 1; k1 < K; ++k1) x[k1] = cmul(x[k1], w72[s * k1]);
+    for (int k1 = 1; k1 < K; ++k1) {
+      if constexpr (G == 2) {
+        const cx<T> w = {T(Tw<72>::t.c[k1]), T(-Tw<72>::t.s[k1])};
+        const cx<T> y = cmul(x[k1], w);
+        x[k1] = csel(s != 0, y, x[k1]);
+      } else {
+        x[k1] = cmul(x[k1], w72[s * k1]);
+      }
+    }
     if constexpr (G >= 8) lane_radix2<T, K, 4, false>(x, s);
     if constexpr (G >= 4) lane_radix2<T, K, 2, false>(x, s);
     lane_radix2<T, K, 1, false>(x, s);
@@ -497,7 +630,15 @@ __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P_rt, int ns_rt, con
     if constexpr (G >= 4) lane_radix2<T, K, 2, true>(x, s);
     if constexpr (G >= 8) lane_radix2<T, K, 4, true>(x, s);
 #pragma unroll
-    for (int j2 = 1; j2 < K; ++j2) x[j2] = cmul(x[j2], w72[j2 * s]);
+    for (int j2 = 1; j2 < K; ++j2) {
+      if constexpr (G == 2) {
+        const cx<T> w = {T(Tw<72>::t.c[j2]), T(-Tw<72>::t.s[j2])};
+        const cx<T> y = cmul(x[j2], w);
+        x[j2] = csel(s != 0, y, x[j2]);
+      } else {
+        x[j2] = cmul(x[j2], w72[j2 * s]);
+      }
+    }
     dft_any<T, K>(x);
     // lane s holds conj(c[s + G kk]);  X[g^{-(s + G kk)}] = v0 + c
 #pragma unroll
@@ -517,11 +658,16 @@ __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P_rt, int ns_rt, con
       const int b = item / NP;
       const int k = b % ns;
       const int base = (b - k) * R + k;
-      int oi = gis;
+      if constexpr (G <= 4) {
+        if constexpr (NBG > 1) rader_scatter<T, G, K, 0, ZP>(Z, out[i], base, ns, p, s);
+        else rader_scatter<T, G, K, 0, ZP>(Z, x, base, ns, p, s);
+      } else {
+        int oi = gis;
 #pragma unroll
-      for (int kk = 0; kk < K; ++kk) {
-        Z[(base + oi * ns) * ZP + p] = (NBG > 1) ? out[i][kk] : x[kk];
-        oi = (oi * giG) % R;
+        for (int kk = 0; kk < K; ++kk) {
+          Z[(base + oi * ns) * ZP + p] = (NBG > 1) ? out[i][kk] : x[kk];
+          oi = (oi * giG) % R;
+        }
       }
       if (s == 0) Z[base * ZP + p] = out0[i];
     }
@@ -781,7 +927,7 @@ __device__ __forceinline__ void pack(T* X, cx<T>* Z, int kind, const AX& ax) {
 // Z -> X, through registers, optionally dividing by the eigenvalue sum.
 template <typename T, int NP, int NT, int PMAX, int kind, class AX, int ZP = NP>
 __device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const AX& ax, const PassArgs& a,
-                                         int64_t l0, bool scale) {
+                                         int64_t l0, bool scale, const T* lts = nullptr) {
   constexpr int TL = 2 * NP;
   constexpr int XP = 2 * ZP;
   constexpr int E = ((AX::ct ? AX::Nc : PMAX) * TL + NT - 1) / NT;
@@ -814,8 +960,9 @@ __device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const AX& ax, const Pas
       const int k = item / TL;
       T x = unpack_value<T, ZP, kind>(Z, ax, t, k);
       if (scale) {
-        const T lam = lam_other + lt[k];
-        x = (dead_line || (zero_line && k == 0)) ? T(0) : x / lam;
+        const bool zero = dead_line || (zero_line && k == 0);
+        if (lts) x = zero ? T(0) : quick_div(x, lam_other + lts[k]);
+        else x = zero ? T(0) : x / (lam_other + lt[k]);
       }
       v[i] = x;
     }
@@ -863,8 +1010,11 @@ __device__ __forceinline__ void dct1_mirror(cx<T>* Z, int n, int M) {
 // In-place division of a DCT-I result by the eigenvalue sums, written to the
 // mirrored rows as well, so that the result is at once the input of the
 // inverse DCT-I.
+// lts: the eigenvalues of this axis staged in LDS by a specialised kernel
+// (else null: read from global memory, IEEE division).
 template <typename T, int NP, int NT, class AX, int ZP = NP>
-__device__ __forceinline__ void dct1_scale_mirror(T* X, const AX& ax, const PassArgs& a, int64_t l0) {
+__device__ __forceinline__ void dct1_scale_mirror(T* X, const AX& ax, const PassArgs& a, int64_t l0,
+                                                  const T* lts = nullptr) {
   constexpr int TL = 2 * NP;
   constexpr int XP = 2 * ZP;
   static_assert(NT % TL == 0, "thread count must be a multiple of the tile width");
@@ -882,12 +1032,23 @@ __device__ __forceinline__ void dct1_scale_mirror(T* X, const AX& ax, const Pass
     else if (la) lam_other = la[l];
   }
   const bool zero_line = a.singular && (l == 0);
-  for (int it = tid; it < n * TL; it += NT) {
-    const int k = it / TL;
-    const int xi_k = k * XP + t;
-    const T x = (dead_line || (zero_line && k == 0)) ? T(0) : X[xi_k] / (lam_other + lt[k]);
-    X[xi_k] = x;
-    if (k >= 1 && k <= n - 2) X[(M - k) * XP + t] = x;
+  if (lts) {
+#pragma unroll 4
+    for (int it = tid; it < n * TL; it += NT) {
+      const int k = it / TL;
+      const int xi_k = k * XP + t;
+      const T x = (dead_line || (zero_line && k == 0)) ? T(0) : quick_div(X[xi_k], lam_other + lts[k]);
+      X[xi_k] = x;
+      if (k >= 1 && k <= n - 2) X[(M - k) * XP + t] = x;
+    }
+  } else {
+    for (int it = tid; it < n * TL; it += NT) {
+      const int k = it / TL;
+      const int xi_k = k * XP + t;
+      const T x = (dead_line || (zero_line && k == 0)) ? T(0) : X[xi_k] / (lam_other + lt[k]);
+      X[xi_k] = x;
+      if (k >= 1 && k <= n - 2) X[(M - k) * XP + t] = x;
+    }
   }
   __syncthreads();
 }
@@ -908,7 +1069,8 @@ __device__ __forceinline__ int64_t xcd_tile(unsigned b, unsigned G) {
 // the compile-time kind of a specialised kernel, or -2 for the run-time kind.
 template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM, class AX, class ST, int K, int ZP>
 __device__ __forceinline__ void transform_phase(T* X, cx<T>* Z, const AX& ax, const PassArgs& a, int64_t l0,
-                                                int kind_rt, bool scale, int kind_next, bool& mirrored) {
+                                                int kind_rt, bool scale, int kind_next, bool& mirrored,
+                                                const T* lts = nullptr) {
   const int kind = K >= 0 ? K : kind_rt;
   const cx<T>* tw = static_cast<const cx<T>*>(ax.d.tw);
   const cx<T>* cs = static_cast<const cx<T>*>(ax.d.cs);
@@ -939,15 +1101,31 @@ __device__ __forceinline__ void transform_phase(T* X, cx<T>* Z, const AX& ax, co
   }
   if (inplace && kind == K_DCT1) {
     if (scale) {
-      dct1_scale_mirror<T, NP, NT, AX, ZP>(X, ax, a, l0);
+      dct1_scale_mirror<T, NP, NT, AX, ZP>(X, ax, a, l0, lts);
       mirrored = kind_next == K_DCT1;
     }
   } else {
-    if constexpr (K >= 0) unpack_k<T, NP, NT, PMAX, K, AX, ZP>(Z, X, ax, a, l0, scale);
+    if constexpr (K >= 0) unpack_k<T, NP, NT, PMAX, K, AX, ZP>(Z, X, ax, a, l0, scale, lts);
     else unpack<T, NP, NT, PMAX>(Z, X, kind, ax, a, l0, scale);
   }
 }
 
+
+// Bytes of LDS a specialised kernel uses for its tile / work buffer (the
+// larger of n real rows and P complex rows at pitch ZP), rounded to 16.
+template <typename T, int N, int P, int ZP>
+constexpr int spec_main_lds() {
+  const int xs = 2 * ZP * N, zs = 2 * ZP * P;
+  return ((xs > zs ? xs : zs) * int(sizeof(T)) + 15) / 16 * 16;
+}
+
+// Whether a fused specialised kernel stages the axis's eigenvalues in LDS:
+// only when that does not cost a second workgroup per CU (160 KB of LDS).
+template <typename T, int N, int P, int ZP>
+constexpr bool spec_stage_lam() {
+  constexpr int half = 80 * 1024;
+  return spec_main_lds<T, N, P, ZP>() + N * int(sizeof(T)) <= half || spec_main_lds<T, N, P, ZP>() > half;
+}
 
 // One sweep over tile `tile`.  AX, KF, KB, ST: length view, forward and
 // inverse kinds (-1: no inverse) and stage list of a kernel specialised for
@@ -1039,6 +1217,14 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
       }
     }
   };
+  // a fused specialised kernel keeps this axis's eigenvalues in LDS behind
+  // the tile (spec_main_lds bytes in)
+  T* lts = nullptr;
+  if constexpr (AX::ct && KB >= 0 && spec_stage_lam<T, AX::Nc, AX::Pc, ZP>()) {
+    lts = reinterpret_cast<T*>(smem + spec_main_lds<T, AX::Nc, AX::Pc, ZP>());
+    const T* lt = static_cast<const T*>(a.lam_this);
+    for (int i = int(threadIdx.x); i < AX::Nc; i += NT) lts[i] = lt[i];
+  }
   if (mode == 1) {
     if (a.src_f64) fast_load(double(0), off_c, xi_c);
     else fast_load(float(0), off_c, xi_c);
@@ -1054,7 +1240,7 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
   // ---- forward transform, and optionally eigenvalue division + inverse transform.
   bool mirrored = false;  // the middle step already built the DCT-I input
   if constexpr (KF >= 0) {
-    transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, KF, ZP>(X, Z, ax, a, l0, KF, KB >= 0, KB, mirrored);
+    transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, KF, ZP>(X, Z, ax, a, l0, KF, KB >= 0, KB, mirrored, lts);
     if constexpr (KB >= 0)
       transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, KB, ZP>(X, Z, ax, a, l0, KB, false, -1, mirrored);
   } else {
