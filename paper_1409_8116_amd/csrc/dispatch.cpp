@@ -28,14 +28,14 @@ MPOIS_SPECS(MPOIS_DECL_SPEC)
 
 namespace {
 struct SpecInfo {
-  int f64, np, nt, rader, n, M, P, kf, kb;
+  int f64, np, nt, rader, pad, n, M, P, kf, kb;
   std::vector<int> radices;
   hipError_t (*launch)(const PassArgs&, hipStream_t, size_t);
   hipError_t (*prepare)();
 };
 const SpecInfo kSpecs[] = {
-#define X(ID, T, NP, NT, RADER, SLIM, N, M, P, KF, KB, ...) \
-  {sizeof(T) == 8, NP, NT, RADER, N, M, P, KF, KB, {__VA_ARGS__}, &launch_spec_##ID, &prepare_spec_##ID},
+#define X(ID, T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, ...) \
+  {sizeof(T) == 8, NP, NT, RADER, PAD, N, M, P, KF, KB, {__VA_ARGS__}, &launch_spec_##ID, &prepare_spec_##ID},
     MPOIS_SPECS(X)
 #undef X
 };
@@ -120,21 +120,22 @@ void spec_shape(int i, int* f64, int* np, int* nt, int* n) {
   *n = kSpecs[i].n;
 }
 
-// LDS of a specialised kernel: rows of ZP = NP + 1 complex values (the
-// padded pitch of spec_pitch in line_pass.h), n real rows or P complex rows,
-// as spec_main_lds in line_pass.h computes it.
+// LDS of a specialised kernel: rows of ZP = NP + PAD complex values, n real
+// rows or P complex rows, as spec_main_lds in line_pass.h computes it.
 size_t spec_lds(int i) {
   const SpecInfo& c = kSpecs[i];
   const size_t es = c.f64 ? 8 : 4;
-  const size_t zp = size_t(c.np) + 1;
+  const size_t zp = size_t(c.np) + size_t(c.pad);
   const size_t xs = 2 * zp * size_t(c.n);
   const size_t zs = 2 * zp * size_t(c.P);
   const size_t main = ((xs > zs ? xs : zs) * es + 15) / 16 * 16;
-  // fused kernels stage the axis's eigenvalues behind the tile when that
-  // keeps two workgroups per CU (spec_stage_lam in line_pass.h)
+  // behind the tile: the lane-ordered Rader constants (spec_ctab_lds), and
+  // for fused kernels the axis's eigenvalues when that keeps two workgroups
+  // per CU (spec_stage_lam in line_pass.h)
+  const size_t ctab = c.rader ? 144 * 2 * es : 0;
   const size_t half = 80 * 1024, lam = size_t(c.n) * es;
-  const bool stage = c.kb >= 0 && (main + lam <= half || main > half);
-  return main + (stage ? lam : 0);
+  const bool stage = c.kb >= 0 && (main + ctab + lam <= half || main + ctab > half);
+  return main + ctab + (stage ? lam : 0);
 }
 
 hipError_t launch_spec(int i, const PassArgs& a, hipStream_t s) {

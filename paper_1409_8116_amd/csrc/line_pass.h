@@ -448,24 +448,27 @@ __device__ __forceinline__ cx<T> w2h(int j, int h) {
 }
 
 // One radix-2 step of a DFT of length G spread over G lanes (one value per
-// lane, K independent columns).  DIF (first=false): top lane x + x', bottom
-// lane (x' - x) w.  DIT (first=true): top x + w x', bottom x' - w x.
+// lane, K independent columns), partner lane s ^ H, w = e^{-2 pi i (s mod H)/(2H)}.
+// DIF (DIT=false): top lane x + x', bottom lane (x' - x) w.
+// DIT (DIT=true):  top lane x + w x', bottom lane x' - w x.
+// Both are written without per-value selects: with weff = 1 on the top lane
+// and w on the bottom one, DIF is (x' + sg x) weff and DIT exchanges
+// z = x weff and forms z' + sg z (sg = +1 top, -1 bottom).
 template <typename T, int K, int H, bool DIT>
 __device__ __forceinline__ void lane_radix2(cx<T>* x, int s) {
   const bool top = (s & H) == 0;
   const T sg = top ? T(1) : T(-1);
-  const cx<T> w = w2h<T>(s & (H - 1), H);
+  const cx<T> weff = csel(top, cx<T>{T(1), T(0)}, w2h<T>(s & (H - 1), H));
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const cx<T> xp = lane_xor_cx<H>(x[k]);
     if constexpr (!DIT) {
+      const cx<T> xp = lane_xor_cx<H>(x[k]);
       const cx<T> t = {xp.re + sg * x[k].re, xp.im + sg * x[k].im};
-      x[k] = (H == 1) ? t : cmul(t, csel(top, cx<T>{T(1), T(0)}, w));
+      x[k] = (H == 1) ? t : cmul(t, weff);
     } else {
-      // top: x + w x' ; bottom: x' - w x  ==  u + sg * (w v) with (u, v) = top ? (x, x') : (x', x)
-      const cx<T> u = csel(top, x[k], xp), v = csel(top, xp, x[k]);
-      const cx<T> wv = (H == 1) ? v : cmul(w, v);
-      x[k] = {u.re + sg * wv.re, u.im + sg * wv.im};
+      const cx<T> z = (H == 1) ? x[k] : cmul(x[k], weff);
+      const cx<T> zp = lane_xor_cx<H>(z);
+      x[k] = {zp.re + sg * z.re, zp.im + sg * z.im};
     }
   }
 }
@@ -551,9 +554,13 @@ __device__ __forceinline__ void rader_scatter(cx<T>* Z, const cx<T>* x, int base
   if constexpr (KK + 1 < K) rader_scatter<T, G, K, KK + 1, ZP>(Z, x, base, ns, p, s);
 }
 
+// ctab: the kernel spectrum and twiddles in LDS, laid out [k1][s] for this G
+// (entry k1 G + s: dhat[k1 + K bitrev(s)], then 72 entries e^{-2 pi i s k1/72}),
+// so each lane reads them at its own base plus immediate offsets; null: the
+// global table tab (dhat[0..71], then e^{-2 pi i j/72}).
 template <typename T, int NP, int NT, int PMAX, int G, int PC = 0, int NSC = 0, int ZP = NP>
 __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P_rt, int ns_rt, const cx<T>* __restrict__ tw,
-                                              const cx<T>* __restrict__ tab) {
+                                              const cx<T>* __restrict__ tab, const cx<T>* ctab = nullptr) {
   static_assert(G == 2 || G == 4 || G == 8, "lanes per Rader butterfly");
   constexpr int R = 73, L = 72, K = L / G;
   constexpr int NBG = (((PC ? PC : PMAX) / R) * NP * G + NT - 1) / NT;
@@ -614,7 +621,7 @@ __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P_rt, int ns_rt, con
         const cx<T> y = cmul(x[k1], w);
         x[k1] = csel(s != 0, y, x[k1]);
       } else {
-        x[k1] = cmul(x[k1], w72[s * k1]);
+        x[k1] = cmul(x[k1], ctab ? ctab[72 + k1 * G + s] : w72[s * k1]);
       }
     }
     if constexpr (G >= 8) lane_radix2<T, K, 4, false>(x, s);
@@ -624,7 +631,7 @@ __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P_rt, int ns_rt, con
     const int k2 = lane_bitrev<G>(s);
     out0[i] = v0 + x[0];
 #pragma unroll
-    for (int k1 = 0; k1 < K; ++k1) x[k1] = conj(cmul(x[k1], dhat[k1 + K * k2]));
+    for (int k1 = 0; k1 < K; ++k1) x[k1] = conj(cmul(x[k1], ctab ? ctab[k1 * G + s] : dhat[k1 + K * k2]));
     // second length-72 DFT: across lanes first (bit-reversed in, natural out)
     lane_radix2<T, K, 1, true>(x, s);
     if constexpr (G >= 4) lane_radix2<T, K, 2, true>(x, s);
@@ -636,7 +643,7 @@ __device__ __forceinline__ void stage_rader73(cx<T>* Z, int P_rt, int ns_rt, con
         const cx<T> y = cmul(x[j2], w);
         x[j2] = csel(s != 0, y, x[j2]);
       } else {
-        x[j2] = cmul(x[j2], w72[j2 * s]);
+        x[j2] = cmul(x[j2], ctab ? ctab[72 + j2 * G + s] : w72[j2 * s]);
       }
     }
     dft_any<T, K>(x);
@@ -725,22 +732,22 @@ struct StageList {
 // accumulate as the host builds them (ns * (R - 1) twiddles per stage, the
 // Rader constants first in the constant table).
 template <typename T, int NP, int ZP, int NT, int RADER, int P, int NS, int TWOFF, int R, int... Rest>
-__device__ __forceinline__ void dft_engine_ct(cx<T>* Z, const cx<T>* __restrict__ tw,
-                                              const cx<T>* __restrict__ cs) {
+__device__ __forceinline__ void dft_engine_ct(cx<T>* Z, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ cs,
+                                              const cx<T>* __restrict__ ctab) {
   if constexpr (R == 73) {
     static_assert(RADER != 0, "Rader stage needs a Rader kernel shape");
-    stage_rader73<T, NP, NT, P, RADER, P, NS, ZP>(Z, P, NS, tw + TWOFF, cs);
+    stage_rader73<T, NP, NT, P, RADER, P, NS, ZP>(Z, P, NS, tw + TWOFF, cs, ctab);
   } else {
     stage<T, R, NP, NT, P, P, NS, ZP>(Z, P, NS, tw + TWOFF);
   }
   if constexpr (sizeof...(Rest) > 0)
-    dft_engine_ct<T, NP, ZP, NT, RADER, P, NS * R, TWOFF + NS * (R - 1), Rest...>(Z, tw, cs);
+    dft_engine_ct<T, NP, ZP, NT, RADER, P, NS * R, TWOFF + NS * (R - 1), Rest...>(Z, tw, cs, ctab);
 }
 
 template <typename T, int NP, int ZP, int NT, int RADER, int P, int... Rs>
-__device__ __forceinline__ void dft_engine_list(cx<T>* Z, const cx<T>* __restrict__ tw,
-                                                const cx<T>* __restrict__ cs, StageList<Rs...>) {
-  dft_engine_ct<T, NP, ZP, NT, RADER, P, 1, 0, Rs...>(Z, tw, cs);
+__device__ __forceinline__ void dft_engine_list(cx<T>* Z, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ cs,
+                                                const cx<T>* __restrict__ ctab, StageList<Rs...>) {
+  dft_engine_ct<T, NP, ZP, NT, RADER, P, 1, 0, Rs...>(Z, tw, cs, ctab);
 }
 
 // Element k of the length-M DFT of pair p after dft_full.
@@ -961,7 +968,7 @@ __device__ __forceinline__ void unpack_k(cx<T>* Z, T* X, const AX& ax, const Pas
       T x = unpack_value<T, ZP, kind>(Z, ax, t, k);
       if (scale) {
         const bool zero = dead_line || (zero_line && k == 0);
-        if (lts) x = zero ? T(0) : quick_div(x, lam_other + lts[k]);
+        if constexpr (AX::ct) x = zero ? T(0) : quick_div(x, lam_other + (lts ? lts[k] : lt[k]));
         else x = zero ? T(0) : x / (lam_other + lt[k]);
       }
       v[i] = x;
@@ -1011,7 +1018,8 @@ __device__ __forceinline__ void dct1_mirror(cx<T>* Z, int n, int M) {
 // mirrored rows as well, so that the result is at once the input of the
 // inverse DCT-I.
 // lts: the eigenvalues of this axis staged in LDS by a specialised kernel
-// (else null: read from global memory, IEEE division).
+// (else null: read from global memory).  Specialised kernels (compile-time
+// length) divide with quick_div, the generic shapes with IEEE division.
 template <typename T, int NP, int NT, class AX, int ZP = NP>
 __device__ __forceinline__ void dct1_scale_mirror(T* X, const AX& ax, const PassArgs& a, int64_t l0,
                                                   const T* lts = nullptr) {
@@ -1032,12 +1040,13 @@ __device__ __forceinline__ void dct1_scale_mirror(T* X, const AX& ax, const Pass
     else if (la) lam_other = la[l];
   }
   const bool zero_line = a.singular && (l == 0);
-  if (lts) {
+  if constexpr (AX::ct) {
+    const T* lk = lts ? lts : lt;
 #pragma unroll 4
     for (int it = tid; it < n * TL; it += NT) {
       const int k = it / TL;
       const int xi_k = k * XP + t;
-      const T x = (dead_line || (zero_line && k == 0)) ? T(0) : quick_div(X[xi_k], lam_other + lts[k]);
+      const T x = (dead_line || (zero_line && k == 0)) ? T(0) : quick_div(X[xi_k], lam_other + lk[k]);
       X[xi_k] = x;
       if (k >= 1 && k <= n - 2) X[(M - k) * XP + t] = x;
     }
@@ -1070,7 +1079,7 @@ __device__ __forceinline__ int64_t xcd_tile(unsigned b, unsigned G) {
 template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM, class AX, class ST, int K, int ZP>
 __device__ __forceinline__ void transform_phase(T* X, cx<T>* Z, const AX& ax, const PassArgs& a, int64_t l0,
                                                 int kind_rt, bool scale, int kind_next, bool& mirrored,
-                                                const T* lts = nullptr) {
+                                                const T* lts = nullptr, const cx<T>* ctab = nullptr) {
   const int kind = K >= 0 ? K : kind_rt;
   const cx<T>* tw = static_cast<const cx<T>*>(ax.d.tw);
   const cx<T>* cs = static_cast<const cx<T>*>(ax.d.cs);
@@ -1096,7 +1105,7 @@ __device__ __forceinline__ void transform_phase(T* X, cx<T>* Z, const AX& ax, co
       }
       __syncthreads();
     }
-    if constexpr (ST::count > 0) dft_engine_list<T, NP, ZP, NT, RADER, AX::Pc>(Z, tw, cs, ST{});
+    if constexpr (ST::count > 0) dft_engine_list<T, NP, ZP, NT, RADER, AX::Pc>(Z, tw, cs, ctab, ST{});
     else dft_engine<T, NP, NT, PMAX, RADER, SLIM>(Z, ax.P(), ax.d.nstages, ax.d.st, tw, cs);
   }
   if (inplace && kind == K_DCT1) {
@@ -1119,12 +1128,20 @@ constexpr int spec_main_lds() {
   return ((xs > zs ? xs : zs) * int(sizeof(T)) + 15) / 16 * 16;
 }
 
+// LDS of a specialised kernel behind the tile: the Rader constants (144
+// complex values) of a kernel with a Rader stage.
+template <typename T, int RADER>
+constexpr int spec_ctab_lds() {
+  return RADER ? 144 * 2 * int(sizeof(T)) : 0;
+}
+
 // Whether a fused specialised kernel stages the axis's eigenvalues in LDS:
 // only when that does not cost a second workgroup per CU (160 KB of LDS).
-template <typename T, int N, int P, int ZP>
+template <typename T, int N, int P, int ZP, int RADER>
 constexpr bool spec_stage_lam() {
   constexpr int half = 80 * 1024;
-  return spec_main_lds<T, N, P, ZP>() + N * int(sizeof(T)) <= half || spec_main_lds<T, N, P, ZP>() > half;
+  constexpr int base = spec_main_lds<T, N, P, ZP>() + spec_ctab_lds<T, RADER>();
+  return base + N * int(sizeof(T)) <= half || base > half;
 }
 
 // One sweep over tile `tile`.  AX, KF, KB, ST: length view, forward and
@@ -1219,9 +1236,18 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
   };
   // a fused specialised kernel keeps this axis's eigenvalues in LDS behind
   // the tile (spec_main_lds bytes in)
+  // and a kernel with a Rader stage its constants, in lane order (after the
+  // 144 entries of the global layout: the G = 2 block, then the G = 4 block)
   T* lts = nullptr;
-  if constexpr (AX::ct && KB >= 0 && spec_stage_lam<T, AX::Nc, AX::Pc, ZP>()) {
-    lts = reinterpret_cast<T*>(smem + spec_main_lds<T, AX::Nc, AX::Pc, ZP>());
+  cx<T>* ctab = nullptr;
+  if constexpr (AX::ct && RADER != 0) {
+    static_assert(RADER == 2 || RADER == 4, "lane-ordered Rader constants exist for 2 and 4 lanes");
+    ctab = reinterpret_cast<cx<T>*>(smem + spec_main_lds<T, AX::Nc, AX::Pc, ZP>());
+    const cx<T>* src = static_cast<const cx<T>*>(a.ax.cs) + (RADER == 2 ? 144 : 288);
+    for (int i = int(threadIdx.x); i < 144; i += NT) ctab[i] = src[i];
+  }
+  if constexpr (AX::ct && KB >= 0 && spec_stage_lam<T, AX::Nc, AX::Pc, ZP, RADER>()) {
+    lts = reinterpret_cast<T*>(smem + spec_main_lds<T, AX::Nc, AX::Pc, ZP>() + spec_ctab_lds<T, RADER>());
     const T* lt = static_cast<const T*>(a.lam_this);
     for (int i = int(threadIdx.x); i < AX::Nc; i += NT) lts[i] = lt[i];
   }
@@ -1240,9 +1266,11 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
   // ---- forward transform, and optionally eigenvalue division + inverse transform.
   bool mirrored = false;  // the middle step already built the DCT-I input
   if constexpr (KF >= 0) {
-    transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, KF, ZP>(X, Z, ax, a, l0, KF, KB >= 0, KB, mirrored, lts);
+    transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, KF, ZP>(X, Z, ax, a, l0, KF, KB >= 0, KB, mirrored, lts,
+                                                                   ctab);
     if constexpr (KB >= 0)
-      transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, KB, ZP>(X, Z, ax, a, l0, KB, false, -1, mirrored);
+      transform_phase<T, NP, NT, PMAX, RADER, SLIM, AX, ST, KB, ZP>(X, Z, ax, a, l0, KB, false, -1, mirrored, lts,
+                                                                     ctab);
   } else {
     const int nphase = a.kind_b >= 0 ? 2 : 1;
     for (int phase = 0; phase < nphase; ++phase) {
@@ -1365,42 +1393,37 @@ hipError_t launch_lp_batch(const BatchPassArgs& b, int blocks, hipStream_t s, si
   return hipGetLastError();
 }
 
-// LDS row pitch (complex values) of the specialised kernels: one complex
-// value of padding per row, so that rows written by consecutive lanes of the
-// contiguous-axis load start on different banks.
-template <typename T, int NP>
-constexpr int spec_pitch() {
-  return NP + 1;
-}
-
 // A kernel specialised for one transform: line length N, DFT length M, work
 // length P, kinds KF / KB (KB = -1: no inverse) and the Stockham stage list,
 // all compile-time; everything else (arrays, strides, tables, eigenvalues)
 // comes from the pass description as in line_pass.
-template <typename T, int NP, int NT, int RADER, int SLIM, int N, int M, int P, int KF, int KB, int... Rs>
+// PAD: complex values of padding per LDS row (pitch NP + PAD): staggers the
+// rows that consecutive lanes write in the contiguous-axis load over the
+// banks.
+template <typename T, int NP, int NT, int RADER, int SLIM, int PAD, int N, int M, int P, int KF, int KB, int... Rs>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM, RADER>::v, 8)))
 line_pass_spec(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  line_pass_body<T, NP, NT, P, RADER, SLIM, Ax<N, M, P>, KF, KB, StageList<Rs...>, spec_pitch<T, NP>()>(
+  line_pass_body<T, NP, NT, P, RADER, SLIM, Ax<N, M, P>, KF, KB, StageList<Rs...>, NP + PAD>(
       a, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
-template <typename T, int NP, int NT, int RADER, int SLIM, int N, int M, int P, int KF, int KB, int... Rs>
+template <typename T, int NP, int NT, int RADER, int SLIM, int PAD, int N, int M, int P, int KF, int KB, int... Rs>
 hipError_t launch_spec_t(const PassArgs& a, hipStream_t s, size_t lds) {
   constexpr int64_t TL = 2 * NP;
   if (a.ax.n != N || a.ax.M != M || a.ax.P != P || a.kind_f != KF || a.kind_b != KB ||
       a.ax.nstages != int(sizeof...(Rs)))
     return hipErrorInvalidValue;  // the description must be the one this kernel was compiled for
   const int64_t blocks = (a.nlines + TL - 1) / TL;
-  hipLaunchKernelGGL((line_pass_spec<T, NP, NT, RADER, SLIM, N, M, P, KF, KB, Rs...>), dim3(unsigned(blocks)),
+  hipLaunchKernelGGL((line_pass_spec<T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, Rs...>), dim3(unsigned(blocks)),
                      dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int NP, int NT, int RADER, int SLIM, int N, int M, int P, int KF, int KB, int... Rs>
+template <typename T, int NP, int NT, int RADER, int SLIM, int PAD, int N, int M, int P, int KF, int KB, int... Rs>
 hipError_t prepare_spec_t() {
   return hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&line_pass_spec<T, NP, NT, RADER, SLIM, N, M, P, KF, KB, Rs...>),
+      reinterpret_cast<const void*>(&line_pass_spec<T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, Rs...>),
       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 

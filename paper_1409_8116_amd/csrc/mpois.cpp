@@ -506,6 +506,18 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
       for (auto& x : d) cs.push_back(x / double(L));
       // twiddles e^{-2 pi i j / L} of the two-level length-L DFT
       for (int j = 0; j < L; ++j) cs.emplace_back(cospi_frac(2 * j, L), -sinpi_frac(2 * j, L));
+      // the same constants in lane order for G = 2 and G = 4 lanes per
+      // butterfly (entry k1 G + s): dhat[k1 + K bitrev(s)], then the twiddle
+      // e^{-2 pi i s k1 / L}; the kernels stage one block in LDS
+      const size_t d0 = cs.size() - size_t(2 * L);  // dhat, just written
+      for (int G : {2, 4}) {
+        const int K = L / G;
+        auto bitrev = [G](int x) { return G == 2 ? x : ((x & 1) << 1) | (x >> 1); };
+        for (int k1 = 0; k1 < K; ++k1)
+          for (int sl = 0; sl < G; ++sl) cs.push_back(cs[d0 + k1 + K * bitrev(sl)]);
+        for (int k1 = 0; k1 < K; ++k1)
+          for (int sl = 0; sl < G; ++sl) cs.emplace_back(cospi_frac(2 * sl * k1, L), -sinpi_frac(2 * sl * k1, L));
+      }
     }
     ns *= R;
   }

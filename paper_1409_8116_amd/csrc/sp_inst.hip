@@ -14,16 +14,16 @@ namespace mpois {
 #define MPOIS_PASTE(a, b) MPOIS_PASTE2(a, b)
 
 hipError_t MPOIS_PASTE(launch_spec_, MPOIS_SPEC)(const PassArgs& a, hipStream_t s, size_t lds) {
-#define X(ID, T, NP, NT, RADER, SLIM, N, M, P, KF, KB, ...) \
-  if constexpr (ID == MPOIS_SPEC) return launch_spec_t<T, NP, NT, RADER, SLIM, N, M, P, KF, KB, __VA_ARGS__>(a, s, lds);
+#define X(ID, T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, ...) \
+  if constexpr (ID == MPOIS_SPEC) return launch_spec_t<T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, __VA_ARGS__>(a, s, lds);
   MPOIS_SPECS(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
 hipError_t MPOIS_PASTE(prepare_spec_, MPOIS_SPEC)() {
-#define X(ID, T, NP, NT, RADER, SLIM, N, M, P, KF, KB, ...) \
-  if constexpr (ID == MPOIS_SPEC) return prepare_spec_t<T, NP, NT, RADER, SLIM, N, M, P, KF, KB, __VA_ARGS__>();
+#define X(ID, T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, ...) \
+  if constexpr (ID == MPOIS_SPEC) return prepare_spec_t<T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, __VA_ARGS__>();
   MPOIS_SPECS(X)
 #undef X
   return hipErrorInvalidValue;
