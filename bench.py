@@ -1,23 +1,25 @@
 """Benchmark of the fast Poisson solve on one MI355X.
 
-Default workload (`--workload neumann512`): 512^3 all-Neumann vertex grid
-(DCT-I on every axis), second-order finite differences, h = 1/511, right-hand
-side = 64 seeded Gaussian blobs (sigma 0.02) minus its mean.  One step = one
-solve in FP32 with FP64 residual refinement (fixed number of corrections): the
-forward transforms, the eigenvalue division with the zero mode removed, the
-inverse transforms, the FP64 stencil residual, the zero-mode reductions and
-the FP64 update.  The plain FP64 solve of the same input is timed beside it,
-and the CPU oracle (dense FP64 transform matrices) is timed on the host on the
-same input.
+Headline (one JSON line on stdout): the 512^3 all-Neumann vertex grid (DCT-I
+on every axis), second-order finite differences, h = 1/511, right-hand side =
+64 seeded Gaussian blobs (sigma 0.02) minus their trapezoid-weighted mean.
+One step = one solve in FP32 with FP64 residual refinement (fixed number of
+corrections): forward transforms, eigenvalue division with the zero mode
+removed, inverse transforms, FP64 stencil residual, zero-mode reductions and
+FP64 update.  The plain FP64 solve of the same input is timed beside it, and
+the CPU oracle (dense FP64 transform matrices) on the host.
 
-Other workloads (one JSON line each, same keys):
-  periodic32  32^3 periodic FD, FP64, one solve per step, eager and graph-replayed
+The same line carries the other workloads under "configs" (default
+`--workload all`; `--workload NAME` prints that one alone):
+  periodic32  32^3 periodic FD, FP64: us per solve, eager and graph-replayed
   mixed256    256^3 staggered P/D/N box, FP64 and FP32, FD and pseudo-spectral
-  batch2048   2048 independent 2D grids (sides 64..1024), FP32 + refinement, one batched launch set
-  channel     1024x512x256 channel, graph-captured FP32 + refinement, stream of RHS
+  batch2048   2048 independent 2D grids (sides 64..1024), FP32 + refinement,
+              autotuned plans
+  channel     1024x512x256 channel, graph-captured FP32 + refinement, a stream
+              of right-hand sides
   copy        plain 1 GiB device-to-device copy (calibrates the HBM byte counters)
-
-Prints one JSON line per workload on stdout; progress goes to stderr.
+Each entry: ms per step, grid points/s, algorithmic HBM GB/s and the error
+against the oracle on its sample.  Progress goes to stderr.
 """
 
 import argparse
@@ -58,7 +60,7 @@ def timed(fn, steps, warmup):
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("line_pass.h", "cfgs.h"):
+    for f in ("line_pass.h", "cfgs.h", "specs.h"):
         with open(os.path.join(ROOT, "paper_1409_8116_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -76,13 +78,23 @@ def measured_traffic(kernel):
     for ln in lines:
         if ln.startswith("traffic:"):
             kv = dict(x.split("=", 1) for x in ln[len("traffic:"):].strip().split(" ") if "=" in x)
-            if kv.get("sources") == want and kernel.replace(" ", "") in ln.replace(" ", ""):
+            if kv.get("sources") == want and kv.get("kernel", "").replace(" ", "") == kernel.replace(" ", ""):
                 return float(kv["bytes_per_launch"])
     return None
 
 
+def kernel_name(k):
+    if k == 100:
+        return "resid_kernel"
+    if k == 101:
+        return "finalize_kernel"
+    import paper_1409_8116_amd as mp
+    return mp.kernel_shape_name(k)
+
+
 def kernel_roofline(records, reps):
-    """Dominant kernel (largest total time) of profiled executes: bytes / duration."""
+    """Dominant kernel (largest total time) of profiled executes: algorithmic
+    bytes of its launches / their HIP-event durations."""
     by = {}
     for r in records:
         e = by.setdefault(r["kernel"], {"ms": 0.0, "bytes": 0.0, "count": 0})
@@ -99,16 +111,8 @@ def kernel_roofline(records, reps):
             "bytes_per_launch": e["bytes"] / e["count"]}
 
 
-def kernel_name(k):
-    if k == 100:
-        return "resid_kernel"
-    if k == 101:
-        return "finalize_kernel"
-    import paper_1409_8116_amd as mp
-    return mp.kernel_shape_name(k)
-
-
 def profile_plan(make_plan, rhs, reps=3):
+    """Per-launch HIP-event records of `reps` executes of a profiling plan."""
     import torch
     plan = make_plan()
     tmp = torch.empty_like(rhs)
@@ -117,20 +121,28 @@ def profile_plan(make_plan, rhs, reps=3):
         plan.solve(rhs, tmp)
         recs += plan.profile()
     plan.close()
-    return kernel_roofline(recs, reps)
+    return recs, reps
+
+
+def step_gbs(records, reps, ms):
+    """Algorithmic bytes of one step (all launches) / its time."""
+    return sum(r["bytes"] for r in records) / reps / (ms * 1e-3) / 1e9
+
+
+def cpu_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        return os.cpu_count()
 
 
 def cpu_oracle(d, g):
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count()
     axes = oracle.axes_from(d["shape"], d["h"], d["bc"], d["grid"])
     t0 = time.perf_counter()
     ref = oracle.solve(g, axes, d["approx"])
-    return ref, time.perf_counter() - t0, threads
+    return ref, time.perf_counter() - t0, cpu_threads()
 
 
 def rel(a, ref):
@@ -150,7 +162,7 @@ def run_neumann(args):
     import workloads
     import paper_1409_8116_amd as mp
     n = args.n
-    log(f"generating {n}^3 Neumann blob input")
+    log(f"[neumann512] generating {n}^3 Neumann blob input")
     d, g = workloads.neumann_blobs(n, seed=3)
     npts = int(np.prod(d["shape"]))
     rhs = torch.tensor(g, dtype=torch.float64, device="cuda")
@@ -158,38 +170,45 @@ def run_neumann(args):
     phi_64 = torch.empty_like(rhs)
     plan_r = mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, f64_arith=args.f64_arith)
     plan_64 = mp.Plan.from_desc(d, prec="f64")
-    log("timing FP32 + refinement")
+    log("[neumann512] timing FP32 + refinement")
     ms_r, wall_r = timed(lambda: plan_r.solve(rhs, phi_r), args.steps, args.warmup)
     info_r = plan_r.info()
-    log(f"  {ms_r:.3f} ms/solve, rel resid {info_r['rel_resid']:.3e}")
-    log("timing FP64")
+    log(f"[neumann512]   {ms_r:.3f} ms/solve, rel resid {info_r['rel_resid']:.3e}")
+    log("[neumann512] timing FP64")
     ms_64, _ = timed(lambda: plan_64.solve(rhs, phi_64), args.steps, args.warmup)
     info_64 = plan_64.info()
-    log(f"  {ms_64:.3f} ms/solve, rel resid {info_64['rel_resid']:.3e}")
-    roof = profile_plan(lambda: mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, profile=True,
-                                                  f64_arith=args.f64_arith), rhs)
-    roof64 = profile_plan(lambda: mp.Plan.from_desc(d, prec="f64", profile=True), rhs)
-    log(f"dominant kernel (f32r) {roof['kernel']}: {roof['avg_launch_ms']:.3f} ms avg, {roof['achieved']:.0f} GB/s")
-    log(f"dominant kernel (f64) {roof64['kernel']}: {roof64['avg_launch_ms']:.3f} ms avg, {roof64['achieved']:.0f} GB/s")
+    log(f"[neumann512]   {ms_64:.3f} ms/solve, rel resid {info_64['rel_resid']:.3e}")
+    rec_r, reps = profile_plan(lambda: mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, profile=True,
+                                                         f64_arith=args.f64_arith), rhs)
+    rec_64, _ = profile_plan(lambda: mp.Plan.from_desc(d, prec="f64", profile=True), rhs)
+    roof, roof64 = kernel_roofline(rec_r, reps), kernel_roofline(rec_64, reps)
+    log(f"[neumann512] dominant kernel (f32r) {roof['kernel']}: {roof['avg_launch_ms']:.3f} ms avg, "
+        f"{roof['achieved']:.0f} GB/s")
+    log(f"[neumann512] dominant kernel (f64) {roof64['kernel']}: {roof64['avg_launch_ms']:.3f} ms avg, "
+        f"{roof64['achieved']:.0f} GB/s")
     out = base_record(args, "grid points solved/s (FP32+FP64 refinement to 1e-12 rel. error), with HBM GB/s",
                       npts / (ms_r * 1e-3), "points/s", ms_r, "f32+f64",
                       {"workload": f"neumann_vertex_{n}^3_dct1_fd_blobs64", "shape": list(d["shape"]),
                        "bc": "N,N,N (vertex)", "approx": "fd", "refine_corrections": args.max_iter})
+    out["hbm_gbs_step"] = step_gbs(rec_r, reps, ms_r)
     out["fp64_path"] = {"points_per_s": npts / (ms_64 * 1e-3), "ms_per_solve": ms_64,
+                        "hbm_gbs_step": step_gbs(rec_64, reps, ms_64),
                         "speed_ratio_f32r_over_f64": ms_64 / ms_r, "roofline": roof64}
     out["rel_resid"] = {"f32r": info_r["rel_resid"], "f64": info_64["rel_resid"]}
     out["roofline"] = roof
     out["wall_ms_per_step"] = wall_r
     if not args.no_cpu:
-        log("running the CPU oracle on the same input (one full solve)")
+        log("[neumann512] running the CPU oracle on the same input (one full solve)")
         ref, dt, threads = cpu_oracle(d, g)
         err_r, err_64 = rel(phi_r, ref), rel(phi_64, ref)
-        log(f"oracle {dt:.1f} s; rel err f32r {err_r:.3e}, f64 {err_64:.3e}")
+        log(f"[neumann512] oracle {dt:.1f} s; rel err f32r {err_r:.3e}, f64 {err_64:.3e}")
         out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
                                "sample": f"one full {n}^3 solve of the same input (dense FP64 transform "
                                          f"matrices, {dt:.1f} s)"}
         out["rel_err_vs_oracle"] = {"f32r": err_r, "f64": err_64}
-    return [out]
+    plan_r.close()
+    plan_64.close()
+    return out
 
 
 def run_periodic32(args):
@@ -206,23 +225,27 @@ def run_periodic32(args):
     ms_e, _ = timed(lambda: eager.solve(rhs, phi), steps, 50)
     phi_g = torch.empty_like(rhs)
     ms_g, _ = timed(lambda: graph.solve(rhs, phi_g), steps, 50)
-    out = base_record(args, "grid points solved/s", npts / (ms_g * 1e-3), "points/s", ms_g, "f64",
-                      {"workload": "periodic_32^3_fd_fp64", "shape": [32, 32, 32]})
-    out["us_per_solve"] = {"eager": ms_e * 1e3, "graph": ms_g * 1e3}
-    out["roofline"] = profile_plan(lambda: mp.Plan.from_desc(d, prec="f64", profile=True), rhs)
+    log(f"[periodic32] {ms_e * 1e3:.1f} us eager, {ms_g * 1e3:.1f} us graph-replayed")
+    recs, reps = profile_plan(lambda: mp.Plan.from_desc(d, prec="f64", profile=True), rhs)
+    out = {"workload": "periodic_32^3_fd_fp64", "ms_per_solve": ms_g, "points_per_s": npts / (ms_g * 1e-3),
+           "us_per_solve": {"eager": ms_e * 1e3, "graph": ms_g * 1e3},
+           "hbm_gbs_step": step_gbs(recs, reps, ms_g), "roofline": kernel_roofline(recs, reps),
+           "note": "launch-latency bound; 2.6 MB per solve stays in cache, so GB/s is not an HBM figure"}
     if not args.no_cpu:
         ref, dt, threads = cpu_oracle(d, g)
         out["rel_err_vs_oracle"] = {"eager": rel(phi, ref), "graph": rel(phi_g, ref)}
         out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
                                "sample": "one 32^3 solve"}
-    return [out]
+    eager.close()
+    graph.close()
+    return out
 
 
 def run_mixed256(args):
     import torch
     import workloads
     import paper_1409_8116_amd as mp
-    outs = []
+    outs = {}
     for approx in ("fd", "ps"):
         d, g, _ = workloads.mixed_modes(256, seed=2, approx=approx)
         npts = int(np.prod(d["shape"]))
@@ -235,14 +258,18 @@ def run_mixed256(args):
             phi = torch.empty_like(rhs)
             plan = mp.Plan.from_desc(d, prec=prec)
             ms, _ = timed(lambda: plan.solve(rhs, phi), args.steps, args.warmup)
-            out = base_record(args, "grid points solved/s", npts / (ms * 1e-3), "points/s", ms, prec,
-                              {"workload": f"mixed_256^3_P-Ds-Ns_{approx}_{prec}", "shape": [256] * 3})
-            out["roofline"] = profile_plan(lambda: mp.Plan.from_desc(d, prec=prec, profile=True), rhs)
+            recs, reps = profile_plan(lambda: mp.Plan.from_desc(d, prec=prec, profile=True), rhs)
+            o = {"workload": f"mixed_256^3_P-Ds-Ns_{approx}_{prec}", "ms_per_solve": ms,
+                 "points_per_s": npts / (ms * 1e-3), "hbm_gbs_step": step_gbs(recs, reps, ms),
+                 "roofline": kernel_roofline(recs, reps)}
             if ref is not None:
-                out["rel_err_vs_oracle"] = rel(phi, ref)
-                out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
-                                       "sample": f"one 256^3 {approx} solve"}
-            outs.append(out)
+                o["rel_err_vs_oracle"] = rel(phi, ref)
+                o["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+                                     "sample": f"one 256^3 {approx} solve"}
+            log(f"[mixed256] {approx} {prec}: {ms:.3f} ms, {o['hbm_gbs_step']:.0f} GB/s"
+                + (f", rel err {o['rel_err_vs_oracle']:.2e}" if ref is not None else ""))
+            outs[f"{approx}_{prec}"] = o
+            plan.close()
     return outs
 
 
@@ -252,29 +279,35 @@ def run_batch(args):
     import paper_1409_8116_amd as mp
     descs = workloads.batch_2d(count=2048, seed=4)
     npts = sum(int(np.prod(d["shape"])) for d in descs)
-    log(f"batch: 2048 grids, {npts:.3e} points; generating right-hand sides")
+    log(f"[batch2048] 2048 grids, {npts:.3e} points; generating right-hand sides")
     rhs = [torch.tensor(workloads.batch_rhs(d, i), dtype=torch.float64, device="cuda") for i, d in enumerate(descs)]
     phi = [torch.empty_like(r) for r in rhs]
     t0 = time.perf_counter()
-    plan = mp.BatchPlan(descs, prec="f32r", max_iter=args.max_iter)
-    log(f"batch plan built in {time.perf_counter() - t0:.1f} s")
+    plan = mp.BatchPlan(descs, prec="f32r", max_iter=args.max_iter, tune=True)
+    tplan = time.perf_counter() - t0
+    log(f"[batch2048] tuned batch plan built in {tplan:.1f} s")
     ms, _ = timed(lambda: plan.solve(rhs, phi), args.steps, args.warmup)
     info = plan.info()
-    out = base_record(args, "grid points solved/s", npts / (ms * 1e-3), "points/s", ms, "f32+f64",
-                      {"workload": "batch_2048x2D_64-1024_f32r", "grids": 2048, "points": npts})
-    out["rel_resid_worst"] = info["rel_resid"]
+    # algorithmic bytes: 2D F32R with K corrections, 32 + 64 K bytes per point (unfused model)
+    gbs = npts * (32 + 64 * args.max_iter) / (ms * 1e-3) / 1e9
+    out = {"workload": "batch_2048x2D_64-1024_f32r_tuned", "grids": 2048, "points": npts, "ms_per_step": ms,
+           "points_per_s": npts / (ms * 1e-3), "hbm_gbs_model": gbs, "plan_build_s": tplan,
+           "rel_resid_worst": info["rel_resid"]}
+    log(f"[batch2048] {ms:.2f} ms per batch, worst rel resid {info['rel_resid']:.2e}")
     if not args.no_cpu:
-        worst, tsum, nsub = 0.0, 0.0, 0
-        for i in range(0, 2048, 64):
+        worst, tsum, nsub, threads = 0.0, 0.0, 0, 1
+        for i in range(0, 2048, 32):
             d = descs[i]
             ref, dt, threads = cpu_oracle(d, rhs[i].cpu().numpy())
             worst = max(worst, rel(phi[i], ref))
             tsum += dt
             nsub += int(np.prod(d["shape"]))
-        out["rel_err_vs_oracle_subset32"] = worst
+        out["rel_err_vs_oracle_subset64"] = worst
         out["cpu_baseline"] = {"value": nsub / tsum, "unit": "points/s", "cores": threads, "kind": "oracle",
-                               "sample": "32 of the 2048 grids (every 64th)"}
-    return [out]
+                               "sample": "64 of the 2048 grids (every 32nd)"}
+        log(f"[batch2048] worst rel err over 64 grids {worst:.2e}")
+    plan.close()
+    return out
 
 
 def run_channel(args):
@@ -306,15 +339,19 @@ def run_channel(args):
         if s % 50 == 0 or s == nrhs - 1:
             worst_resid = max(worst_resid, plan.info()["rel_resid"])
     ms = total / nrhs
-    out = base_record(args, "grid points solved/s", npts / (ms * 1e-3), "points/s", ms, "f32+f64",
-                      {"workload": f"channel_1024x512x256_P-Ns-P_graph_f32r_{nrhs}rhs", "shape": list(d["shape"])})
-    out["rel_resid_worst_sampled"] = worst_resid
+    recs, reps = profile_plan(lambda: mp.Plan.from_desc(d, prec="f32r", max_iter=1, profile=True), rhs)
+    out = {"workload": f"channel_1024x512x256_P-Ns-P_graph_f32r_{nrhs}rhs", "ms_per_rhs": ms,
+           "points_per_s": npts / (ms * 1e-3), "hbm_gbs_step": step_gbs(recs, reps, ms),
+           "roofline": kernel_roofline(recs, reps), "rel_resid_worst_sampled": worst_resid}
+    log(f"[channel] {ms:.3f} ms per right-hand side, {out['hbm_gbs_step']:.0f} GB/s")
     if not args.no_cpu:
         ref, dt, threads = cpu_oracle(d, g0.cpu().numpy())
         out["rel_err_vs_oracle_rhs0"] = rel(first, ref)
         out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
                                "sample": "one 1024x512x256 solve (rhs #0)"}
-    return [out]
+        log(f"[channel] rel err rhs #0 {out['rel_err_vs_oracle_rhs0']:.2e}")
+    plan.close()
+    return out
 
 
 def run_copy(args):
@@ -325,13 +362,11 @@ def run_copy(args):
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     ms, _ = timed(lambda: dst.copy_(src), max(args.steps, 3), 1)
-    out = base_record(args, "device copy GB/s", 2 * nbytes / (ms * 1e-3) / 1e9, "GB/s", ms, "f64",
-                      {"workload": "copy_1GiB"})
-    return [out]
+    return {"workload": "copy_1GiB", "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
-WORKLOADS = {"copy": run_copy, "neumann512": run_neumann, "periodic32": run_periodic32, "mixed256": run_mixed256,
-             "batch2048": run_batch, "channel": run_channel}
+SECONDARY = {"periodic32": run_periodic32, "mixed256": run_mixed256, "batch2048": run_batch,
+             "channel": run_channel}
 
 
 def main():
@@ -339,7 +374,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="neumann512", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "neumann512", "copy"] + sorted(SECONDARY))
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--max-iter", type=int, default=2)
     ap.add_argument("--nrhs", type=int, default=200)
@@ -353,8 +389,21 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    for rec in WORKLOADS[args.workload](args):
-        print(json.dumps(rec), flush=True)
+    if args.workload == "copy":
+        print(json.dumps(run_copy(args)), flush=True)
+        return
+    if args.workload in SECONDARY:
+        print(json.dumps(SECONDARY[args.workload](args)), flush=True)
+        return
+    rec = run_neumann(args)
+    if args.workload == "all":
+        rec["configs"] = {}
+        for name, fn in SECONDARY.items():
+            log(f"--- {name}")
+            t0 = time.perf_counter()
+            rec["configs"][name] = fn(args)
+            log(f"--- {name} done in {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -149,7 +149,7 @@ def kernel_shape_name(cfg):
         return f"line_pass#{cfg}"
     t = "double" if v[0].value == 8 else "float"
     if cfg >= 200:
-        return f"line_pass_spec<{t}, {v[1].value}, {v[2].value}, n={v[3].value}>"
+        return f"line_pass_spec#{cfg - 200}<{t}, {v[1].value}, {v[2].value}, n={v[3].value}>"
     return f"line_pass<{t}, {v[1].value}, {v[2].value}, {v[3].value}>"
 
 
