@@ -19,6 +19,9 @@ What it computes follows the paper directly:
   boundary closures, its dense assembly and a dense LU solve, used to pin
   Table 4 and as the refinement residual reference.
 
+Beyond the paper's tables: axes with a Dirichlet condition on one face and a
+Neumann condition on the other, and a Helmholtz shift (L - sigma) phi = g.
+
 Everything is float64/complex128 NumPy.  There are no FFT calls, no blocking
 and no reordering beyond the per-axis matrix products.
 """
@@ -28,12 +31,12 @@ from .transforms import (transform_matrix, forward_backward, dft_matrix,
 from .eigen import domain_length, eigenvalues, grid_points
 from .solve import solve, solve_spectrum_scale, zero_mode_is_singular, Axis, axes_from
 from .fd import (apply_laplacian, assemble_1d, assemble, lu_solve, weights,
-                 weighted_mean, residual_eta)
+                 weighted_mean, residual_eta, is_singular)
 
 __all__ = [
     "transform_matrix", "forward_backward", "dft_matrix", "idft_matrix", "KINDS",
     "domain_length", "eigenvalues", "grid_points",
     "solve", "solve_spectrum_scale", "zero_mode_is_singular", "Axis", "axes_from",
     "apply_laplacian", "assemble_1d", "assemble", "lu_solve", "weights",
-    "weighted_mean", "residual_eta",
+    "weighted_mean", "residual_eta", "is_singular",
 ]

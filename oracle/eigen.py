@@ -8,6 +8,12 @@
   finite differences), index k running over the output index of the
   matching forward transform of Table 2.
 
+Axes with a Dirichlet condition on one face and a Neumann condition on the
+other ("DN" / "ND", beyond Tables 3 and 4) have the eigenfunctions
+sin / cos((k+1/2) pi x/L): pseudo-spectral lambda_k = -((k+1/2) pi/L)^2 and
+finite differences lambda_k = -(2 sin(pi (2k+1)/(4n))/dx)^2, with L = n h on
+both grids (vertex: unknowns on the Neumann node and the interior nodes).
+
 Reading of the printed periodic pseudo-spectral cutoff: the two branches of
 Table 3 select the aliased wavenumber min(k, n-k), which is what makes the
 operator real and symmetric under k <-> n-k; the Nyquist mode of an even n
@@ -19,7 +25,7 @@ import numpy as np
 
 def domain_length(bc, grid, n, h):
     """L such that the grid of Section 2.1 with n unknowns has spacing h."""
-    if bc == "P" or grid == "s":
+    if bc == "P" or grid == "s" or bc in ("DN", "ND"):
         return n * h
     if bc == "D":
         return (n + 1) * h
@@ -36,6 +42,10 @@ def grid_points(bc, grid, n, h):
         return j * L / n
     if grid == "s":
         return (j + 0.5) * L / n
+    if bc == "DN":
+        return (j + 1.0) * L / n
+    if bc == "ND":
+        return j * L / n
     if bc == "D":
         return (j + 1.0) * L / (n + 1)
     return j * L / (n - 1)
@@ -58,6 +68,8 @@ def eigenvalues(bc, grid, n, h, approx):
             return -(np.pi * (k + 1).astype(np.float64) / L) ** 2
         if bc == "N":
             return -(np.pi * k.astype(np.float64) / L) ** 2
+        if bc in ("DN", "ND"):
+            return -(np.pi * (k.astype(np.float64) + 0.5) / L) ** 2
         raise ValueError(bc)
     if approx == "fd":
         if bc == "P":
@@ -70,6 +82,8 @@ def eigenvalues(bc, grid, n, h, approx):
             s = _sinpi(k, 2 * (n - 1))
         elif bc == "N" and grid == "s":
             s = _sinpi(k, 2 * n)
+        elif bc in ("DN", "ND"):
+            s = _sinpi(2 * k + 1, 4 * n)
         else:
             raise ValueError((bc, grid))
         return -(2.0 * s / h) ** 2

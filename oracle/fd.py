@@ -12,7 +12,15 @@ eigenvectors are the transforms of Table 2 with the eigenvalues of Table 4
   Neumann regular    phi_{-1} = phi_1,  phi_n = phi_{n-2}    (mirror about the node)
   Neumann stagg.     phi_{-1} = phi_0,  phi_n = phi_{n-1}    (zero flux on the face)
 
-The multi-dimensional operator is the sum over axes (Section 2.3).
+An axis with different conditions on its faces ("DN": Dirichlet low,
+Neumann high; "ND" the reverse) closes each end by that face's rule:
+  regular grid  Dirichlet end: the boundary node is 0 and not an unknown;
+                Neumann end: mirror about the end node (phi_{-1} = phi_1),
+                where phi_1 is the Dirichlet node (0) when n = 1
+  staggered     Dirichlet face: phi_ghost = -phi_end; Neumann: +phi_end
+
+The multi-dimensional operator is the sum over axes (Section 2.3).  A
+Helmholtz shift sigma >= 0 subtracts sigma phi: (L_h - sigma) phi = g.
 
 For singular problems (every axis periodic or Neumann) the solution is fixed
 by the gauge sum_j w_j phi_j = 0 with the weights of ``weights``: 1 per node,
@@ -40,16 +48,26 @@ def _pad_axis(phi, d, bc, grid):
         lo, hi = phi[1], phi[n - 2]
     elif bc == "N" and grid == "s":
         lo, hi = phi[0], phi[n - 1]
+    elif bc in ("DN", "ND") and grid == "v":
+        zero = np.zeros_like(phi[0])
+        if bc == "DN":   # Dirichlet node below index 0; index n-1 is the Neumann node
+            lo, hi = zero, (phi[n - 2] if n >= 2 else zero)
+        else:            # index 0 is the Neumann node; Dirichlet node above index n-1
+            lo, hi = (phi[1] if n >= 2 else zero), zero
+    elif bc in ("DN", "ND") and grid == "s":
+        sl, sh = (-1.0, 1.0) if bc == "DN" else (1.0, -1.0)
+        lo, hi = sl * phi[0], sh * phi[n - 1]
     else:
         raise ValueError((bc, grid))
     out = np.concatenate([lo[None], phi, hi[None]], axis=0)
     return np.moveaxis(out, 0, d)
 
 
-def apply_laplacian(phi, axes):
-    """L_h phi = sum_d (phi_{j+1} - 2 phi_j + phi_{j-1}) / h_d^2 with the closures above."""
+def apply_laplacian(phi, axes, shift=0.0):
+    """L_h phi - shift phi, L_h phi = sum_d (phi_{j+1} - 2 phi_j + phi_{j-1}) / h_d^2
+    with the closures above."""
     phi = np.asarray(phi, dtype=np.float64)
-    out = np.zeros_like(phi)
+    out = -float(shift) * phi
     for d, a in enumerate(axes):
         p = _pad_axis(phi, d, a.bc, a.grid)
         n = phi.shape[d]
@@ -85,6 +103,12 @@ def assemble(axes):
     return big
 
 
+def is_singular(axes, shift=0.0):
+    """The operator has the constant null vector: no shift, every axis periodic
+    or Neumann on both faces."""
+    return shift == 0.0 and all(a.bc in ("P", "N") for a in axes)
+
+
 def weights(axes):
     """Gauge / compatibility weights w (product of per-axis weights)."""
     w = np.ones([a.n for a in axes])
@@ -105,16 +129,17 @@ def weighted_mean(x, axes):
     return float(np.sum(w * x) / np.sum(w))
 
 
-def lu_solve(g, axes):
-    """Dense LU solve of L phi = g; bordered system [[L, 1], [w^T, 0]] when singular.
+def lu_solve(g, axes, shift=0.0):
+    """Dense LU solve of (L - shift) phi = g; bordered system [[L, 1], [w^T, 0]]
+    when singular.
 
     Returns (phi, m_g): m_g is the multiplier of the bordered system, i.e. the
     weighted mean removed from g (0 for nonsingular problems).
     """
     g = np.asarray(g, dtype=np.float64)
-    L = assemble(axes)
+    L = assemble(axes) - float(shift) * np.eye(g.size)
     rhs = g.reshape(-1)
-    if all(a.bc in ("P", "N") for a in axes):
+    if is_singular(axes, shift):
         N = rhs.size
         w = weights(axes).reshape(-1)
         A = np.zeros((N + 1, N + 1))
@@ -126,14 +151,15 @@ def lu_solve(g, axes):
     return np.linalg.solve(L, rhs).reshape(g.shape), 0.0
 
 
-def residual_eta(g, phi, axes):
-    """Scaled residual ||g_c - L phi|| / (||L|| ||phi|| + ||g_c||), ||L|| <= sum_d 4/h_d^2.
+def residual_eta(g, phi, axes, shift=0.0):
+    """Scaled residual ||g_c - (L - shift) phi|| / (||L - shift|| ||phi|| + ||g_c||),
+    ||L - shift|| <= sum_d 4/h_d^2 + shift.
 
     g_c is g with its weighted mean removed when the problem is singular.
     """
     g = np.asarray(g, dtype=np.float64)
-    if all(a.bc in ("P", "N") for a in axes):
+    if is_singular(axes, shift):
         g = g - weighted_mean(g, axes)
-    r = g - apply_laplacian(phi, axes)
-    lnorm = sum(4.0 / (a.h * a.h) for a in axes)
+    r = g - apply_laplacian(phi, axes, shift)
+    lnorm = sum(4.0 / (a.h * a.h) for a in axes) + float(shift)
     return float(np.linalg.norm(r) / (lnorm * np.linalg.norm(phi) + np.linalg.norm(g)))

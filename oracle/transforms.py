@@ -6,9 +6,17 @@ transform named, written straight from its definition:
 * DFT / IDFT        -- Eqs. (5)-(6) of Section 2.1: the forward transform
   carries the 1/n factor, the inverse is unscaled.
 * DST-I/II/III, DCT-I/II/III -- Table 1 (unnormalised sums).
+* DST-IV, DCT-IV -- not in Table 1; written in the same unnormalised form
+  (2 sum_j f_j sin / cos(pi (j+1/2)(k+1/2)/n)).  They are the transforms of
+  a staggered axis with a Dirichlet condition on one face and a Neumann
+  condition on the other (a combination beyond the paper's Table 2).
 
 ``forward_backward`` pairs them with a boundary condition and grid as in
-Table 2, including the scale factor in front of each backward transform.
+Table 2, including the scale factor in front of each backward transform;
+an axis with different conditions on its two faces ("DN": Dirichlet at the
+low end, Neumann at the high end, or "ND") gets the transform whose basis
+vectors are the sampled eigenfunctions sin / cos((k+1/2) pi x/L) of that
+axis, with the same backward factor convention.
 
 Angles are formed from exact integer products reduced modulo their period
 before the single multiplication by pi, so every entry is the correctly
@@ -18,7 +26,9 @@ rounded value of its definition to within one or two ulps.
 import numpy as np
 
 # (bc, grid) pairs with a transform of their own; periodic axes ignore the grid.
-KINDS = (("P", "v"), ("D", "v"), ("D", "s"), ("N", "v"), ("N", "s"))
+# "DN" / "ND": different conditions on the low and high face of the axis.
+KINDS = (("P", "v"), ("D", "v"), ("D", "s"), ("N", "v"), ("N", "s"),
+         ("DN", "v"), ("DN", "s"), ("ND", "v"), ("ND", "s"))
 
 
 def _sinpi(num, den):
@@ -84,6 +94,18 @@ def dct3(n):
     return t
 
 
+def dst4(n):
+    """DST-IV, unnormalised like Table 1: 2 sum_j f_j sin(pi (j+1/2)(k+1/2)/n)."""
+    k, j = _kj(n)
+    return 2.0 * _sinpi((2 * j + 1) * (2 * k + 1), 4 * n)
+
+
+def dct4(n):
+    """DCT-IV, unnormalised like Table 1: 2 sum_j f_j cos(pi (j+1/2)(k+1/2)/n)."""
+    k, j = _kj(n)
+    return 2.0 * _cospi((2 * j + 1) * (2 * k + 1), 4 * n)
+
+
 def dft_matrix(n):
     """Eq. (6): fhat_k = (1/n) sum_j f_j exp(-2 pi i k j/n)."""
     k, j = _kj(n)
@@ -98,8 +120,8 @@ def idft_matrix(n):
     return np.cos(ang) + 1j * np.sin(ang)
 
 
-_TABLE1 = {"DST-I": dst1, "DST-II": dst2, "DST-III": dst3,
-           "DCT-I": dct1, "DCT-II": dct2, "DCT-III": dct3,
+_TABLE1 = {"DST-I": dst1, "DST-II": dst2, "DST-III": dst3, "DST-IV": dst4,
+           "DCT-I": dct1, "DCT-II": dct2, "DCT-III": dct3, "DCT-IV": dct4,
            "DFT": dft_matrix, "IDFT": idft_matrix}
 
 
@@ -126,4 +148,20 @@ def forward_backward(bc, grid, n):
         return dct1(n), dct1(n) / (2.0 * (n - 1))
     if bc == "N" and grid == "s":
         return dct2(n), dct3(n) / (2.0 * n)
+    # Different conditions on the two faces.  Vertex grid, Dirichlet low /
+    # Neumann high: unknowns at x = (j+1) h, j < n (the Neumann node x = L = n h
+    # included); the eigenvectors sin((k+1/2) pi (j+1)/n) are orthogonal with
+    # weight 1/2 on that end node, which makes the forward transform the
+    # DST-III of Table 1 and its inverse the DST-II.  Neumann low / Dirichlet
+    # high: unknowns at x = j h, cos((k+1/2) pi j/n), weight 1/2 at x = 0:
+    # DCT-III forward, DCT-II backward.  Staggered: DST-IV / DCT-IV, each its
+    # own inverse up to 1/(2n).
+    if bc == "DN" and grid == "v":
+        return dst3(n), dst2(n) / (2.0 * n)
+    if bc == "ND" and grid == "v":
+        return dct3(n), dct2(n) / (2.0 * n)
+    if bc == "DN" and grid == "s":
+        return dst4(n), dst4(n) / (2.0 * n)
+    if bc == "ND" and grid == "s":
+        return dct4(n), dct4(n) / (2.0 * n)
     raise ValueError(f"unknown boundary condition / grid {bc!r}/{grid!r}")

@@ -21,6 +21,8 @@ from oracle.solve import Axis
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KINDS = [("P", "v"), ("D", "v"), ("D", "s"), ("N", "v"), ("N", "s")]
+# different conditions on the two faces of an axis (Dirichlet low / Neumann high, and the reverse)
+MIXED = [("DN", "v"), ("DN", "s"), ("ND", "v"), ("ND", "s")]
 SIZES_P1 = list(range(1, 33)) + [48, 64, 100, 127, 511, 512, 1021]
 
 
@@ -31,14 +33,17 @@ def _valid(bc, grid, n):
 # ---------------------------------------------------------------- Table 1 vs scipy.fft
 @pytest.mark.parametrize("n", [2, 3, 4, 5, 8, 9, 16, 31, 64, 100])
 def test_table1_matches_scipy(n):
-    """Table 1 sums equal scipy's unnormalised DCT/DST types 1-3 (column by column)."""
+    """Table 1 sums equal scipy's unnormalised DCT/DST types 1-3 (column by column), and
+    the type-IV transforms of the mixed-face axes equal scipy's type 4."""
     eye = np.eye(n)
     pairs = [("DCT-II", lambda x: sfft.dct(x, type=2, axis=0)),
              ("DCT-III", lambda x: sfft.dct(x, type=3, axis=0)),
              ("DST-I", lambda x: sfft.dst(x, type=1, axis=0)),
              ("DST-II", lambda x: sfft.dst(x, type=2, axis=0)),
              ("DST-III", lambda x: sfft.dst(x, type=3, axis=0)),
-             ("DCT-I", lambda x: sfft.dct(x, type=1, axis=0))]
+             ("DCT-I", lambda x: sfft.dct(x, type=1, axis=0)),
+             ("DST-IV", lambda x: sfft.dst(x, type=4, axis=0)),
+             ("DCT-IV", lambda x: sfft.dct(x, type=4, axis=0))]
     for name, lib in pairs:
         mine = T.transform_matrix(name, n)
         ref = lib(eye)
@@ -54,7 +59,7 @@ def test_dft_pair_matches_numpy(n):
 
 
 # ---------------------------------------------------------------- Table 2 normalisations
-@pytest.mark.parametrize("bc,grid", KINDS)
+@pytest.mark.parametrize("bc,grid", KINDS + MIXED)
 def test_table2_backward_inverts_forward(bc, grid):
     """Table 2: the scaled backward transform is the inverse of the forward one."""
     for n in SIZES_P1:
@@ -66,7 +71,7 @@ def test_table2_backward_inverts_forward(bc, grid):
 
 
 # ---------------------------------------------------------------- Table 4 vs the stencil
-@pytest.mark.parametrize("bc,grid", KINDS)
+@pytest.mark.parametrize("bc,grid", KINDS + MIXED)
 def test_table4_eigenvalues_of_stencil_matrix(bc, grid):
     """The assembled Eq. (FD2) matrix has exactly the eigenvalues printed in Table 4."""
     for n in [1, 2, 3, 4, 5, 8, 13, 32]:
@@ -79,7 +84,7 @@ def test_table4_eigenvalues_of_stencil_matrix(bc, grid):
         assert np.allclose(lam_mat, lam_table, atol=1e-11 / h ** 2, rtol=1e-12), (n,)
 
 
-@pytest.mark.parametrize("bc,grid", KINDS)
+@pytest.mark.parametrize("bc,grid", KINDS + MIXED)
 def test_backward_columns_are_stencil_eigenvectors(bc, grid):
     """Column k of the backward transform is an eigenvector of L with Table 4's lambda_k
     (pins the index pairing between Tables 2 and 4)."""
@@ -96,7 +101,7 @@ def test_backward_columns_are_stencil_eigenvectors(bc, grid):
 
 # ---------------------------------------------------------------- FD solve vs dense LU
 def _all_axes_combos(ns):
-    for kinds in itertools.product(KINDS, repeat=len(ns)):
+    for kinds in itertools.product(KINDS + MIXED, repeat=len(ns)):
         yield [Axis(b, g, n, 1.0 / (n + 1.3 * i + 0.7)) for i, ((b, g), n) in enumerate(zip(kinds, ns))]
 
 
@@ -193,10 +198,14 @@ def _eigfun(bc, grid, m, x, L):
         return np.cos(2 * np.pi * m * x / L), -(2 * np.pi * m / L) ** 2
     if bc == "D":
         return np.sin(np.pi * m * x / L), -(np.pi * m / L) ** 2
+    if bc == "DN":  # zero at x = 0, zero slope at x = L
+        return np.sin((m + 0.5) * np.pi * x / L), -((m + 0.5) * np.pi / L) ** 2
+    if bc == "ND":  # zero slope at x = 0, zero at x = L
+        return np.cos((m + 0.5) * np.pi * x / L), -((m + 0.5) * np.pi / L) ** 2
     return np.cos(np.pi * m * x / L), -(np.pi * m / L) ** 2
 
 
-@pytest.mark.parametrize("bc,grid", KINDS)
+@pytest.mark.parametrize("bc,grid", KINDS + MIXED)
 def test_ps_exact_on_continuous_eigenfunctions(bc, grid):
     """Pseudo-spectral solve of a sampled continuous eigenfunction of d2/dx2 returns
     g / lambda_continuous: pins Table 3 together with the grid positions and L."""
@@ -207,7 +216,8 @@ def test_ps_exact_on_continuous_eigenfunctions(bc, grid):
         # grid spacing must be h
         if n > 1:
             assert np.allclose(np.diff(x), h)
-        modes = {"P": range(1, (n + 1) // 2), "D": range(1, n + 1), "N": range(1, n)}[bc]
+        modes = {"P": range(1, (n + 1) // 2), "D": range(1, n + 1), "N": range(1, n),
+                 "DN": range(0, n), "ND": range(0, n)}[bc]
         for m in modes:
             g, lam = _eigfun(bc, grid, m, x, L)
             phi = oracle.solve(g, [Axis(bc, grid, n, h)], "ps")
@@ -259,7 +269,9 @@ def _fd_error(kind, n):
         phi = np.sin(np.pi * x) * np.exp(x)
         g = np.exp(x) * ((1 - np.pi ** 2) * np.sin(np.pi * x) + 2 * np.pi * np.cos(np.pi * x))
     else:
-        h = 1.0 / (n - 1) if grid == "v" else 1.0 / n
+        # Neumann on both faces, or one Dirichlet face: x^2 (1-x)^2 has zero value
+        # and zero slope at both ends of [0, 1]
+        h = 1.0 / (n - 1) if (grid == "v" and bc == "N") else 1.0 / n
         x = oracle.grid_points(bc, grid, n, h)
         phi = x ** 2 * (1 - x) ** 2
         g = 2 - 12 * x + 12 * x ** 2
@@ -270,7 +282,7 @@ def _fd_error(kind, n):
     return np.max(np.abs(num - phi))
 
 
-@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("kind", KINDS + MIXED)
 def test_fd_second_order_convergence(kind):
     """Eq. (FD2) is second order: halving h divides the error by about 4."""
     e1, e2 = _fd_error(kind, 64), _fd_error(kind, 128)
@@ -357,3 +369,50 @@ def test_generated_singular_rhs_are_compatible():
         if all(b in ("P", "N") for b in dd["bc"]):
             ax = oracle.axes_from(dd["shape"], dd["h"], dd["bc"], dd["grid"])
             assert abs(oracle.weighted_mean(gi, ax)) <= 1e-14, (i, dd)
+
+
+# ---------------------------------------------------------------- mixed faces and the Helmholtz shift
+@pytest.mark.parametrize("ns", [(1,), (2,), (5,), (3, 4), (4, 3, 2)])
+def test_helmholtz_shift_matches_dense_lu(ns):
+    """(L - sigma) phi = g: the transform solve with the shifted divisor equals the
+    dense LU solve of the shifted stencil, for every kind combination including
+    mixed faces; with sigma > 0 nothing is singular (no gauge row)."""
+    rng = np.random.default_rng(100 + sum(ns))
+    for axes in _all_axes_combos(ns):
+        if any(not _valid(a.bc, a.grid, a.n) for a in axes):
+            continue
+        sigma = 3.7
+        g = rng.standard_normal(ns)
+        phi = oracle.solve(g, axes, "fd", shift=sigma)
+        ref, mg = oracle.lu_solve(g, axes, shift=sigma)
+        assert mg == 0.0
+        assert np.max(np.abs(phi - ref)) <= 1e-11 * np.max(np.abs(ref)), [(a.bc, a.grid) for a in axes]
+        assert oracle.residual_eta(g, phi, axes, shift=sigma) <= 1e-14
+
+
+@pytest.mark.parametrize("bc,grid", KINDS + MIXED)
+def test_helmholtz_ps_continuous_eigenfunction(bc, grid):
+    """Pseudo-spectral (d2/dx2 - sigma) phi = g on a sampled eigenfunction: phi = g / (lambda - sigma)."""
+    n, h, sigma = 9, 0.2, 2.5
+    L = oracle.domain_length(bc, grid, n, h)
+    x = oracle.grid_points(bc, grid, n, h)
+    m = 0 if bc in ("DN", "ND") else (1 if bc != "D" else 2)
+    g, lam = _eigfun(bc, grid, m, x, L)
+    phi = oracle.solve(g, [Axis(bc, grid, n, h)], "ps", shift=sigma)
+    assert np.allclose(phi, g / (lam - sigma), atol=1e-13 * np.max(np.abs(g)), rtol=0)
+
+
+def test_mixed_face_closures_by_hand():
+    """Boundary rows of the mixed-face stencil written out (h = 1): vertex Dirichlet-low /
+    Neumann-high has rows [-2, 1, 0], [1, -2, 1], [0, 2, -2]; staggered has [-3, 1, 0]
+    (Dirichlet face) and [0, 1, -1] (Neumann face); the reverse orientations mirror them."""
+    dn_v = oracle.assemble_1d("DN", "v", 3, 1.0)
+    assert np.array_equal(dn_v, np.array([[-2, 1, 0], [1, -2, 1], [0, 2, -2]], dtype=float))
+    nd_v = oracle.assemble_1d("ND", "v", 3, 1.0)
+    assert np.array_equal(nd_v, np.array([[-2, 2, 0], [1, -2, 1], [0, 1, -2]], dtype=float))
+    dn_s = oracle.assemble_1d("DN", "s", 3, 1.0)
+    assert np.array_equal(dn_s, np.array([[-3, 1, 0], [1, -2, 1], [0, 1, -1]], dtype=float))
+    nd_s = oracle.assemble_1d("ND", "s", 3, 1.0)
+    assert np.array_equal(nd_s, np.array([[-1, 1, 0], [1, -2, 1], [0, 1, -3]], dtype=float))
+    # one unknown: vertex D|N closes with the Dirichlet node (0) on both sides of the mirror
+    assert np.array_equal(oracle.assemble_1d("DN", "v", 1, 1.0), np.array([[-2.0]]))
