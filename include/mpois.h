@@ -41,8 +41,20 @@ typedef enum {
   MPOIS_ERR_NONFINITE = 6       /* the residual norm is NaN or infinite */
 } mpois_status;
 
-/* Boundary condition of one face (the same on both faces of an axis). */
+/* Boundary condition of one face.  Periodic must be on both faces of an axis;
+ * Dirichlet and Neumann may differ between the two faces. */
 typedef enum { MPOIS_PERIODIC = 0, MPOIS_DIRICHLET = 1, MPOIS_NEUMANN = 2 } mpois_bc;
+
+/* Axis codes of the host helpers mpois_axis_eigenvalues / mpois_axis_plan: an
+ * mpois_bc when both faces agree, else Dirichlet on the low face (index 0) and
+ * Neumann on the high face (DN), or the reverse (ND).  Such an axis has the
+ * eigenfunctions sin / cos((k+1/2) pi x/L) (beyond Tables 2-4 of the paper):
+ * vertex grids transform by DST-III / DCT-III forward and DST-II / DCT-II
+ * backward (unknowns: the interior nodes and the Neumann end node, L = n h),
+ * staggered grids by DST-IV / DCT-IV both ways (L = n h); the finite-difference
+ * eigenvalues are -(2 sin(pi (2k+1)/(4n))/h)^2. */
+#define MPOIS_AXIS_DN 3
+#define MPOIS_AXIS_ND 4
 
 /* Grid of Section 2.1: vertex = the paper's "regular" grid (Dirichlet: interior
  * nodes x_j=(j+1)L/(n+1); Neumann: boundary nodes included, x_j=jL/(n-1));
@@ -65,15 +77,19 @@ typedef enum { MPOIS_F64 = 0, MPOIS_F32 = 1, MPOIS_F32_REFINE = 2 } mpois_prec;
                                    rounded relative to its own size, so a correction contracts the error
                                    by about the FP32 unit roundoff */
 
-/* One grid.  ndim in 1..3; n[d] >= 1 (>= 2 on vertex Neumann axes); h[d] > 0
- * finite; bc[d][0] and bc[d][1] are the two faces of axis d and must be equal
- * (periodic must be on both).  Entries beyond ndim are ignored. */
+/* One grid.  ndim in 1..3; n[d] >= 1 (>= 2 on vertex axes with Neumann on both
+ * faces); h[d] > 0 finite; bc[d][0] and bc[d][1] are the conditions of the low
+ * face (index 0) and the high face of axis d (periodic on both or neither).
+ * shift >= 0 is the Helmholtz sigma: the plan solves (Lap - sigma) phi = rhs
+ * (0: Poisson); with sigma > 0 no problem is singular.  Entries beyond ndim are
+ * ignored. */
 typedef struct {
   int ndim;
   int64_t n[3];
   double h[3];
   int bc[3][2];   /* mpois_bc */
   int grid[3];    /* mpois_grid */
+  double shift;   /* Helmholtz sigma >= 0 */
 } mpois_grid_desc;
 
 typedef struct mpois_plan_s* mpois_plan;
@@ -90,8 +106,8 @@ typedef struct {
  * and rtol (>= 0; 0 disables the check) is compared with the relative residual
  * by mpois_get_info; both are ignored for the other precisions.
  * Allocates the plan's workspace and device tables on the current device.
- * Errors: INVALID (bad descriptor), UNSUPPORTED (different conditions on the
- * two faces of one axis; spectral with refinement), DEVICE (no GPU), NOMEM. */
+ * Errors: INVALID (bad descriptor), UNSUPPORTED (spectral with refinement; an
+ * axis no kernel shape can hold), DEVICE (no GPU), NOMEM. */
 mpois_status mpois_plan_create(const mpois_grid_desc* grid, int approx, int prec, double rtol,
                                int max_iter, unsigned flags, mpois_plan* out);
 
@@ -165,14 +181,16 @@ const char* mpois_status_string(mpois_status s);
 mpois_status mpois_validate(const mpois_grid_desc* grid, int approx, int prec, int max_iter);
 
 /* lambda_k, k = 0..n-1, of one axis as used by the solver (Table 3 or 4,
- * unscaled, FP64), written to out[0..n-1]. */
+ * unscaled, FP64), written to out[0..n-1].  bc: an axis code (mpois_bc or
+ * MPOIS_AXIS_DN / MPOIS_AXIS_ND). */
 mpois_status mpois_axis_eigenvalues(int bc, int grid, int approx, int64_t n, double h, double* out);
 
-/* How one axis is transformed: forward/backward line-transform kinds (0 real
- * DFT to half-complex, 1 its inverse, 2 DCT-II, 3 DCT-III, 4 DST-II, 5 DST-III,
- * 6 DCT-I, 7 DST-I), complex DFT length M, work length P (P > M means a
- * Bluestein convolution), and the radices of the Stockham stages (up to
- * `cap`; *nradix receives the count). */
+/* How one axis is transformed (bc: an axis code): forward/backward
+ * line-transform kinds (0 real DFT to half-complex, 1 its inverse, 2 DCT-II,
+ * 3 DCT-III, 4 DST-II, 5 DST-III, 6 DCT-I, 7 DST-I, 8 DST-IV, 9 DCT-IV),
+ * complex DFT length M, work length P (P > M means a Bluestein convolution),
+ * and the radices of the Stockham stages (up to `cap`; *nradix receives the
+ * count). */
 mpois_status mpois_axis_plan(int bc, int grid, int64_t n, int* kind_fwd, int* kind_bwd, int* M, int* P,
                              int* radices, int cap, int* nradix);
 

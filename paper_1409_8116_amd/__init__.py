@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libmpois.so"
 
 BC = {"P": 0, "D": 1, "N": 2}
+AXIS_CODE = {"P": 0, "D": 1, "N": 2, "DN": 3, "ND": 4}  # axis codes of the host helpers
 GRID = {"v": 0, "s": 1}
 APPROX = {"ps": 0, "fd": 1}
 PREC = {"f64": 0, "f32": 1, "f32r": 2}
@@ -31,7 +32,7 @@ FLAG_PROFILE = 4
 FLAG_F64_ARITH = 8
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory", 4: "device error",
           5: "refinement did not reach rtol", 6: "non-finite residual"}
-KIND_NAMES = ["R2HC", "HC2R", "DCT-II", "DCT-III", "DST-II", "DST-III", "DCT-I", "DST-I"]
+KIND_NAMES = ["R2HC", "HC2R", "DCT-II", "DCT-III", "DST-II", "DST-III", "DCT-I", "DST-I", "DST-IV", "DCT-IV"]
 
 
 class MpoisError(RuntimeError):
@@ -42,7 +43,7 @@ class MpoisError(RuntimeError):
 
 class GridDesc(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double * 3),
-                ("bc", (ctypes.c_int * 2) * 3), ("grid", ctypes.c_int * 3)]
+                ("bc", (ctypes.c_int * 2) * 3), ("grid", ctypes.c_int * 3), ("shift", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -96,7 +97,9 @@ def load_library():
     return lib
 
 
-def make_desc(shape, h, bc, grid):
+def make_desc(shape, h, bc, grid, shift=0.0):
+    """Descriptor of one grid.  bc[i]: "P", "D", "N" (both faces), or a pair of
+    face conditions such as ("D", "N") or the string "DN" (low face first)."""
     d = GridDesc()
     d.ndim = len(shape)
     if not 1 <= d.ndim <= 3:
@@ -105,23 +108,28 @@ def make_desc(shape, h, bc, grid):
         d.n[i] = int(n)
         d.h[i] = float(h[i])
         b = bc[i]
-        lo, hi = (b, b) if isinstance(b, str) else b
+        if isinstance(b, str):
+            lo, hi = (b, b) if len(b) == 1 else (b[0], b[1])
+        else:
+            lo, hi = b
         d.bc[i][0] = BC[lo]
         d.bc[i][1] = BC[hi]
         d.grid[i] = GRID[grid[i]]
+    d.shift = float(shift)
     return d
 
 
-def validate(shape, h, bc, grid, approx="fd", prec="f64", max_iter=1):
+def validate(shape, h, bc, grid, approx="fd", prec="f64", max_iter=1, shift=0.0):
     """Status code of mpois_validate (host only)."""
-    return load_library().mpois_validate(ctypes.byref(make_desc(shape, h, bc, grid)), APPROX[approx], PREC[prec],
-                                         int(max_iter))
+    return load_library().mpois_validate(ctypes.byref(make_desc(shape, h, bc, grid, shift)), APPROX[approx],
+                                         PREC[prec], int(max_iter))
 
 
 def axis_eigenvalues(bc, grid, approx, n, h):
-    """Per-axis eigenvalues the library uses (Table 3 or 4), FP64, host only."""
+    """Per-axis eigenvalues the library uses (Table 3 or 4), FP64, host only.
+    bc: "P", "D", "N", or "DN" / "ND" for different faces."""
     out = np.zeros(int(n), dtype=np.float64)
-    st = load_library().mpois_axis_eigenvalues(BC[bc], GRID[grid], APPROX[approx], int(n), float(h),
+    st = load_library().mpois_axis_eigenvalues(AXIS_CODE[bc], GRID[grid], APPROX[approx], int(n), float(h),
                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if st:
         raise MpoisError(st, "axis_eigenvalues")
@@ -133,7 +141,7 @@ def axis_plan(bc, grid, n):
     vals = [ctypes.c_int() for _ in range(5)]
     rad = (ctypes.c_int * 32)()
     nr = ctypes.c_int()
-    st = load_library().mpois_axis_plan(BC[bc], GRID[grid], int(n), ctypes.byref(vals[0]), ctypes.byref(vals[1]),
+    st = load_library().mpois_axis_plan(AXIS_CODE[bc], GRID[grid], int(n), ctypes.byref(vals[0]), ctypes.byref(vals[1]),
                                         ctypes.byref(vals[2]), ctypes.byref(vals[3]), rad, 32, ctypes.byref(nr))
     if st:
         raise MpoisError(st, "axis_plan")
@@ -176,13 +184,13 @@ class Plan:
     """One grid: mpois_plan_create / mpois_execute / mpois_destroy."""
 
     def __init__(self, shape, h, bc, grid, approx="fd", prec="f64", rtol=0.0, max_iter=2, graph=False, tune=False,
-                 profile=False, f64_arith=False):
+                 profile=False, f64_arith=False, shift=0.0):
         self.lib = load_library()
         self.shape = tuple(int(n) for n in shape)
         self.prec = prec
         flags = (FLAG_GRAPH if graph else 0) | (FLAG_TUNE if tune else 0) | (FLAG_PROFILE if profile else 0) | \
             (FLAG_F64_ARITH if f64_arith else 0)
-        self._desc = make_desc(shape, h, bc, grid)
+        self._desc = make_desc(shape, h, bc, grid, shift)
         handle = ctypes.c_void_p()
         st = self.lib.mpois_plan_create(ctypes.byref(self._desc), APPROX[approx], PREC[prec], float(rtol),
                                         int(max_iter), flags, ctypes.byref(handle))
@@ -192,6 +200,7 @@ class Plan:
 
     @classmethod
     def from_desc(cls, d, prec="f64", **kw):
+        kw.setdefault("shift", d.get("shift", 0.0))
         return cls(d["shape"], d["h"], d["bc"], d["grid"], approx=d["approx"], prec=prec, **kw)
 
     @property
@@ -269,7 +278,7 @@ class BatchPlan:
         approx = approx or self.descs[0]["approx"]
         arr = (GridDesc * len(self.descs))()
         for i, d in enumerate(self.descs):
-            arr[i] = make_desc(d["shape"], d["h"], d["bc"], d["grid"])
+            arr[i] = make_desc(d["shape"], d["h"], d["bc"], d["grid"], d.get("shift", 0.0))
         self._arr = arr
         flags = (FLAG_GRAPH if graph else 0) | (FLAG_TUNE if tune else 0) | (FLAG_F64_ARITH if f64_arith else 0)
         handle = ctypes.c_void_p()

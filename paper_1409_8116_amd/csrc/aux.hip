@@ -1,8 +1,9 @@
 // Auxiliary kernels: FP64 stencil residual with the zero-mode reductions, the
 // fixed-order finalisation of block partial sums, and a zero fill.
 //
-// resid_kernel computes g - m_g - L_h phi for the second-order stencil of
-// Eq. (FD2) with the boundary closure of each axis, and block partial sums of
+// resid_kernel computes g - m_g - (L_h - sigma) phi for the second-order
+// stencil of Eq. (FD2) with the boundary closure of each end of each axis (and
+// the Helmholtz shift sigma), and block partial sums of
 // w phi, w g, r^2 and (g - m_g)^2, where w is the gauge / compatibility weight
 // (1/2 on the end nodes of vertex-grid Neumann axes, 1 elsewhere).  Without
 // phi it only forms the sums of g.
@@ -13,8 +14,10 @@
 namespace mpois {
 
 // ----------------------------------------------------------------------------- residual
-__device__ __forceinline__ double axis_weight(int clo, int64_t i, int64_t n) {
-  return (clo == C_NV && (i == 0 || i == n - 1)) ? 0.5 : 1.0;
+// Gauge weight of node i: 1/2 on an end node closed by a vertex-Neumann mirror
+// (only singular problems use it: Neumann on both faces of such axes).
+__device__ __forceinline__ double axis_weight(int clo, int chi, int64_t i, int64_t n) {
+  return ((clo == C_NV && i == 0) || (chi == C_NV && i == n - 1)) ? 0.5 : 1.0;
 }
 
 constexpr int RESID_NT = 256;
@@ -29,7 +32,8 @@ struct Neighbours {
   double alo, ahi, blo, bhi;
 };
 
-__device__ __forceinline__ Neighbours neighbours(int64_t i, int64_t n, int64_t s, int clo) {
+// clo, chi: closures of the low and the high end of the axis.
+__device__ __forceinline__ Neighbours neighbours(int64_t i, int64_t n, int64_t s, int clo, int chi) {
   Neighbours q{0, 0, 0.0, 0.0, 1.0, 1.0};
   if (clo == C_NONE) return q;
   if (i > 0) {
@@ -46,7 +50,7 @@ __device__ __forceinline__ Neighbours neighbours(int64_t i, int64_t n, int64_t s
   if (i < n - 1) {
     q.dhi = s; q.ahi = 1.0; q.bhi = 0.0;
   } else {
-    switch (clo) {
+    switch (chi) {
       case C_PER: q.dhi = -(n - 1) * s; q.ahi = 1.0; q.bhi = 0.0; break;
       case C_DV: q.bhi = 0.0; break;
       case C_DS: q.bhi = -1.0; break;
@@ -59,7 +63,7 @@ __device__ __forceinline__ Neighbours neighbours(int64_t i, int64_t n, int64_t s
 
 // Second difference along axis 0 from values held in registers.
 __device__ __forceinline__ double second_diff_reg(double lo_v, double c, double hi_v, int64_t i, int64_t n, int clo,
-                                                  double lo_far, double hi_far) {
+                                                  int chi, double lo_far, double hi_far) {
   if (clo == C_NONE) return 0.0;
   double lo, hi;
   if (i > 0) lo = lo_v;
@@ -74,7 +78,7 @@ __device__ __forceinline__ double second_diff_reg(double lo_v, double c, double 
   }
   if (i < n - 1) hi = hi_v;
   else {
-    switch (clo) {
+    switch (chi) {
       case C_PER: hi = hi_far; break;   // phi[0]
       case C_DV: hi = 0.0; break;
       case C_DS: hi = -c; break;
@@ -122,14 +126,14 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
       const int64_t i2 = (rem - i1 * strips) * RESID_NT + threadIdx.x;
       if (i2 >= n2) continue;
       const int64_t base = i1 * n2 + i2;
-      const double w12 = axis_weight(a.clo[1], i1, n1) * axis_weight(a.clo[2], i2, n2);
+      const double w12 = axis_weight(a.clo[1], a.chi[1], i1, n1) * axis_weight(a.clo[2], a.chi[2], i2, n2);
       const int64_t s0 = seg * RESID_SEG;
       const int64_t s1 = (s0 + RESID_SEG < n0) ? s0 + RESID_SEG : n0;
 #pragma unroll 4
       for (int64_t i0 = s0; i0 < s1; ++i0) {
         const double gv = a.g[i0 * plane + base];
         const double gc = gv - mg;
-        s_wg += w12 * axis_weight(a.clo[0], i0, n0) * gv;
+        s_wg += w12 * axis_weight(a.clo[0], a.chi[0], i0, n0) * gv;
         s_g2 += gc * gc;
       }
     }
@@ -146,10 +150,10 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
     const int64_t i2 = (rem - i1 * strips) * RESID_NT + threadIdx.x;
     if (i2 >= n2) continue;
     const int64_t base = i1 * n2 + i2;
-    const double w12 = axis_weight(a.clo[1], i1, n1) * axis_weight(a.clo[2], i2, n2);
+    const double w12 = axis_weight(a.clo[1], a.chi[1], i1, n1) * axis_weight(a.clo[2], a.chi[2], i2, n2);
     // axes 2 and 1: neighbour offsets and weights are fixed for this thread
-    const Neighbours q2 = neighbours(i2, n2, 1, a.clo[2]);
-    const Neighbours q1 = neighbours(i1, n1, n2, a.clo[1]);
+    const Neighbours q2 = neighbours(i2, n2, 1, a.clo[2], a.chi[2]);
+    const Neighbours q1 = neighbours(i1, n1, n2, a.clo[1], a.chi[1]);
     const double* __restrict__ pp = phi + base;
     const double* __restrict__ gp = g + base;
     const double first = pp[0];
@@ -166,12 +170,13 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
       const double d2 = q2.alo * pp[o + q2.dlo] + q2.blo * cur - 2.0 * cur + q2.ahi * pp[o + q2.dhi] + q2.bhi * cur;
       const double d1 = q1.alo * pp[o + q1.dlo] + q1.blo * cur - 2.0 * cur + q1.ahi * pp[o + q1.dhi] + q1.bhi * cur;
       const double lap = a.inv_h2[2] * d2 + a.inv_h2[1] * d1 +
-                         a.inv_h2[0] * second_diff_reg(prev, cur, next, i0, n0, a.clo[0], last, first);
+                         a.inv_h2[0] * second_diff_reg(prev, cur, next, i0, n0, a.clo[0], a.chi[0], last, first) -
+                         a.shift * cur;
       const double gc = gv - mg;
       const double r = gc - lap;
       if (r64) r64[base + o] = r;
       else if (r32) r32[base + o] = float(r);
-      const double w = w12 * axis_weight(a.clo[0], i0, n0);
+      const double w = w12 * axis_weight(a.clo[0], a.chi[0], i0, n0);
       s_wphi += w * cur;
       s_wg += w * gv;
       s_r2 += r * r;

@@ -10,9 +10,12 @@ namespace mpois {
 //   R2HC : real DFT, half-complex output (Re X_0..X_{n/2}, Im X_{(n-1)/2}..Im X_1)
 //   HC2R : inverse of R2HC times n
 //   DCT2 / DCT3 / DST2 / DST3 / DCT1 / DST1 : Table 1 of the paper
+//   DST4 / DCT4 : 2 sum_j x_j sin / cos(pi (j+1/2)(k+1/2)/n), the transforms of
+//                 a staggered axis with a Dirichlet face and a Neumann face
 enum Kind : int {
   K_R2HC = 0, K_HC2R = 1, K_DCT2 = 2, K_DCT3 = 3,
-  K_DST2 = 4, K_DST3 = 5, K_DCT1 = 6, K_DST1 = 7
+  K_DST2 = 4, K_DST3 = 5, K_DCT1 = 6, K_DST1 = 7,
+  K_DST4 = 8, K_DCT4 = 9
 };
 
 constexpr int MAX_STAGES = 16;
@@ -37,7 +40,8 @@ struct AxisDev {
   int pad_;
   const Stage* st;    // nstages entries, device memory
   const void* tw;     // complex, working precision
-  const void* pre;    // e^{-i pi k/(2n)}, k < n (DCT2/DCT3/DST2/DST3 kinds)
+  const void* pre;    // e^{-i pi k/(2n)}, k < n (DCT2/DCT3/DST2/DST3/DST4/DCT4 kinds),
+                      // then entry n = e^{-i pi/(4n)}
   const void* chirp;  // e^{-i pi m^2/M}, m < M (Bluestein)
   const void* bhat;   // DFT_P of the conjugate chirp kernel, divided by P (Bluestein)
   const void* cs;     // odd-radix constants
@@ -84,8 +88,10 @@ struct ResidArgs {
   void* r;              // output residual (or null), float or double
   int r_f64;
   int64_t n[3];
-  int clo[3];
+  int clo[3];           // closure at the low end of each axis
+  int chi[3];           // closure at the high end
   double inv_h2[3];
+  double shift;         // Helmholtz sigma: r = g - m_g - (L_h - sigma) phi
   const double* mg;     // device scalar subtracted from g (or null)
   double* partials;     // 4 per block: sum w phi, sum w g, sum r^2, sum (g-mg)^2
   int singular;         // every axis periodic or Neumann

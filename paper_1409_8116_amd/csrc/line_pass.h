@@ -822,6 +822,15 @@ __device__ __forceinline__ cx<T> pack_value(const T* X, const AX& ax, int m, int
       val = {a.re - b.im, -(a.im + b.re)};  // conj(a + i b)
       break;
     }
+    case K_DST4:
+    case K_DCT4: {
+      // z_m e^{-i pi m/(2n)} for m < n, zero-padded to the DFT length 2n
+      if (m < n) {
+        const cx<T> z = {X[xi<XP>(t0, m)], X[xi<XP>(t1, m)]};
+        val = cmul(z, static_cast<const cx<T>*>(ax.d.pre)[m]);
+      }
+      break;
+    }
     case K_DCT3:
     case K_DST3: {
       // V_k = e^{+i pi k/(2n)} (c_k - i c_{n-k}), c_n = 0; DST3 reverses c first.
@@ -881,6 +890,19 @@ __device__ __forceinline__ T unpack_value(const cx<T>* Z, const AX& ax, int t, i
       const cx<T> z = dft_result<T, ZP>(Z, ax, k, p);
       return w ? -z.im : z.re;
     }
+    case K_DST4:
+    case K_DCT4: {
+      // Q_k = e^{-i pi (2k+1)/(4n)} Z_k; with k' = 2n-1-k, Q_k - Q_k' carries the
+      // DCT-IV of both lines (real: line 0, imaginary: line 1) and Q_k + Q_k'
+      // the DST-IV (line 0: minus the imaginary part, line 1: the real part)
+      const cx<T>* pre = static_cast<const cx<T>*>(ax.d.pre);
+      const cx<T> pk = cmul(pre[k], pre[n]);  // e^{-i pi (2k+1)/(4n)}; pre[n] = e^{-i pi/(4n)}
+      const cx<T> pk2 = {-pk.re, pk.im};      // e^{-i pi (2k'+1)/(4n)} = -conj(pk)
+      const cx<T> Qk = cmul(pk, dft_result<T, ZP>(Z, ax, k, p));
+      const cx<T> Qk2 = cmul(pk2, dft_result<T, ZP>(Z, ax, M - 1 - k, p));
+      if (kind == K_DCT4) return w ? (Qk.im - Qk2.im) : (Qk.re - Qk2.re);
+      return w ? (Qk.re + Qk2.re) : -(Qk.im + Qk2.im);
+    }
     case K_DCT3:
     case K_DST3: {
       const int q = (k & 1) ? n - 1 - (k >> 1) : (k >> 1);
@@ -927,6 +949,8 @@ __device__ __forceinline__ void pack(T* X, cx<T>* Z, int kind, const AX& ax) {
     case K_DST2: pack_k<T, NP, NT, PMAX, K_DST2>(X, Z, ax); break;
     case K_DST3: pack_k<T, NP, NT, PMAX, K_DST3>(X, Z, ax); break;
     case K_DCT1: pack_k<T, NP, NT, PMAX, K_DCT1>(X, Z, ax); break;
+    case K_DST4:
+    case K_DCT4: pack_k<T, NP, NT, PMAX, K_DCT4>(X, Z, ax); break;  // same pre-step
     default: pack_k<T, NP, NT, PMAX, K_DST1>(X, Z, ax); break;
   }
 }
@@ -995,6 +1019,8 @@ __device__ __forceinline__ void unpack(cx<T>* Z, T* X, int kind, const AX& ax,
     case K_DST2: unpack_k<T, NP, NT, PMAX, K_DST2>(Z, X, ax, a, l0, scale); break;
     case K_DST3: unpack_k<T, NP, NT, PMAX, K_DST3>(Z, X, ax, a, l0, scale); break;
     case K_DCT1: unpack_k<T, NP, NT, PMAX, K_DCT1>(Z, X, ax, a, l0, scale); break;
+    case K_DST4: unpack_k<T, NP, NT, PMAX, K_DST4>(Z, X, ax, a, l0, scale); break;
+    case K_DCT4: unpack_k<T, NP, NT, PMAX, K_DCT4>(Z, X, ax, a, l0, scale); break;
     default: unpack_k<T, NP, NT, PMAX, K_DST1>(Z, X, ax, a, l0, scale); break;
   }
 }

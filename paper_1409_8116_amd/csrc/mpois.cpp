@@ -66,9 +66,34 @@ double cospi_frac(int64_t num, int64_t den) {
 }
 
 // ---------------------------------------------------------------------------- per-axis math
-// Table 2: forward / backward line transform of an axis.
+// An axis's conditions as one code: MPOIS_PERIODIC / MPOIS_DIRICHLET /
+// MPOIS_NEUMANN when both faces agree, MPOIS_AXIS_DN (Dirichlet low face,
+// Neumann high face) or MPOIS_AXIS_ND otherwise.
+int axis_code(int lo, int hi) {
+  if (lo == hi) return lo;
+  if (lo == MPOIS_DIRICHLET && hi == MPOIS_NEUMANN) return MPOIS_AXIS_DN;
+  if (lo == MPOIS_NEUMANN && hi == MPOIS_DIRICHLET) return MPOIS_AXIS_ND;
+  return -1;
+}
+
+bool mixed_code(int bc) { return bc == MPOIS_AXIS_DN || bc == MPOIS_AXIS_ND; }
+
+// Table 2: forward / backward line transform of an axis.  Mixed faces (not in
+// Table 2): the transforms whose basis vectors are sin / cos((k+1/2) pi x/L)
+// sampled on the grid -- vertex DST-III / DST-II (Dirichlet low) and
+// DCT-III / DCT-II (Neumann low), staggered DST-IV and DCT-IV.
 void axis_kinds(int bc, int grid, int* kf, int* kb) {
   if (bc == MPOIS_PERIODIC) { *kf = K_R2HC; *kb = K_HC2R; return; }
+  if (bc == MPOIS_AXIS_DN) {
+    if (grid == MPOIS_VERTEX) { *kf = K_DST3; *kb = K_DST2; }
+    else { *kf = K_DST4; *kb = K_DST4; }
+    return;
+  }
+  if (bc == MPOIS_AXIS_ND) {
+    if (grid == MPOIS_VERTEX) { *kf = K_DCT3; *kb = K_DCT2; }
+    else { *kf = K_DCT4; *kb = K_DCT4; }
+    return;
+  }
   if (bc == MPOIS_DIRICHLET) {
     if (grid == MPOIS_VERTEX) { *kf = K_DST1; *kb = K_DST1; }
     else { *kf = K_DST2; *kb = K_DST3; }
@@ -82,19 +107,21 @@ void axis_kinds(int bc, int grid, int* kf, int* kb) {
 int64_t axis_dft_length(int kind, int64_t n) {
   if (kind == K_DCT1) return 2 * (n - 1);
   if (kind == K_DST1) return 2 * (n + 1);
+  if (kind == K_DST4 || kind == K_DCT4) return 2 * n;
   return n;
 }
 
 // Table 2: the factor in front of the backward transform.
 double axis_norm(int bc, int grid, int64_t n) {
   if (bc == MPOIS_PERIODIC) return 1.0 / double(n);
+  if (mixed_code(bc)) return 1.0 / (2.0 * double(n));
   if (bc == MPOIS_DIRICHLET) return grid == MPOIS_VERTEX ? 1.0 / (2.0 * double(n + 1)) : 1.0 / (2.0 * double(n));
   return grid == MPOIS_VERTEX ? 1.0 / (2.0 * double(n - 1)) : 1.0 / (2.0 * double(n));
 }
 
 // Domain length implied by spacing h on the grids of Section 2.1.
 double axis_length(int bc, int grid, int64_t n, double h) {
-  if (bc == MPOIS_PERIODIC || grid == MPOIS_STAGGERED) return double(n) * h;
+  if (bc == MPOIS_PERIODIC || grid == MPOIS_STAGGERED || mixed_code(bc)) return double(n) * h;
   if (bc == MPOIS_DIRICHLET) return double(n + 1) * h;
   return double(n - 1) * h;
 }
@@ -107,6 +134,7 @@ void axis_eigs(int bc, int grid, int approx, int64_t n, double h, double* out) {
     for (int64_t k = 0; k < n; ++k) {
       double w;
       if (bc == MPOIS_PERIODIC) w = 2.0 * M_PI * double(std::min(k, n - k)) / L;
+      else if (mixed_code(bc)) w = M_PI * (double(k) + 0.5) / L;
       else if (bc == MPOIS_DIRICHLET) w = M_PI * double(k + 1) / L;
       else w = M_PI * double(k) / L;
       out[k] = -w * w;
@@ -116,6 +144,7 @@ void axis_eigs(int bc, int grid, int approx, int64_t n, double h, double* out) {
   for (int64_t k = 0; k < n; ++k) {
     double s;
     if (bc == MPOIS_PERIODIC) s = sinpi_frac(k, n);
+    else if (mixed_code(bc)) s = sinpi_frac(2 * k + 1, 4 * n);
     else if (bc == MPOIS_DIRICHLET) s = grid == MPOIS_VERTEX ? sinpi_frac(k + 1, 2 * (n + 1)) : sinpi_frac(k + 1, 2 * n);
     else s = grid == MPOIS_VERTEX ? sinpi_frac(k, 2 * (n - 1)) : sinpi_frac(k, 2 * n);
     const double v = 2.0 * s / h;
@@ -310,7 +339,8 @@ struct SubPlan {
   int ndim = 0;
   int64_t n[3] = {1, 1, 1};     // padded to 3D: leading unit dims
   int64_t npts = 0;
-  int bc[3] = {0, 0, 0}, grid[3] = {0, 0, 0};
+  int bc[3] = {0, 0, 0}, grid[3] = {0, 0, 0};  // bc: axis codes (axis_code)
+  int face[3][2] = {{0, 0}, {0, 0}, {0, 0}};     // conditions of the low / high face
   double h[3] = {1, 1, 1};
   bool singular = false;
   double wsum = 0;              // sum of gauge weights
@@ -530,10 +560,15 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
   if ((st = dev_upload(pl, &at->tw, h)) != MPOIS_OK) return st;
   to_prec(cs, &h);
   if ((st = dev_upload(pl, &at->cs, h)) != MPOIS_OK) return st;
-  // e^{-i pi k/(2n)} for the DCT-II family.
-  if (s.kind_f == K_DCT2 || s.kind_f == K_DST2) {
-    std::vector<std::complex<double>> pre(static_cast<size_t>(n));
+  // e^{-i pi k/(2n)} for the DCT-II/III, DST-II/III and type-IV kinds, then
+  // e^{-i pi/(4n)} (the type-IV post-twiddle's half step)
+  auto uses_pre = [](int k) {
+    return k == K_DCT2 || k == K_DCT3 || k == K_DST2 || k == K_DST3 || k == K_DST4 || k == K_DCT4;
+  };
+  if (uses_pre(s.kind_f) || uses_pre(s.kind_b)) {
+    std::vector<std::complex<double>> pre(static_cast<size_t>(n + 1));
     for (int64_t k = 0; k < n; ++k) pre[k] = {cospi_frac(k, 2 * n), -sinpi_frac(k, 2 * n)};
+    pre[n] = {cospi_frac(1, 4 * n), -sinpi_frac(1, 4 * n)};
     to_prec(pre, &h);
     if ((st = dev_upload(pl, &at->pre, h)) != MPOIS_OK) return st;
   }
@@ -599,10 +634,19 @@ int default_cfg(bool f64, int n, int P, bool rader, bool odd) {
   return best;
 }
 
-int closure_of(int bc, int grid) {
-  if (bc == MPOIS_PERIODIC) return C_PER;
-  if (bc == MPOIS_DIRICHLET) return grid == MPOIS_VERTEX ? C_DV : C_DS;
+// Closure of one end of an axis from that face's condition.  A vertex axis of
+// one unknown with a Neumann face and a Dirichlet face mirrors the Dirichlet
+// node, so both ends see 0.
+int closure_of(int face, int grid) {
+  if (face == MPOIS_PERIODIC) return C_PER;
+  if (face == MPOIS_DIRICHLET) return grid == MPOIS_VERTEX ? C_DV : C_DS;
   return grid == MPOIS_VERTEX ? C_NV : C_NS;
+}
+
+void axis_closures(int lo, int hi, int grid, int64_t n, int* clo, int* chi) {
+  *clo = closure_of(lo, grid);
+  *chi = closure_of(hi, grid);
+  if (lo != hi && grid == MPOIS_VERTEX && n == 1) *clo = *chi = C_DV;
 }
 
 mpois_status validate_one(const mpois_grid_desc* g, int approx, int prec, int max_iter) {
@@ -618,19 +662,20 @@ mpois_status validate_one(const mpois_grid_desc* g, int approx, int prec, int ma
     if (g->grid[d] != MPOIS_VERTEX && g->grid[d] != MPOIS_STAGGERED) return MPOIS_ERR_INVALID;
     if (!(std::isfinite(g->h[d]) && g->h[d] > 0)) return MPOIS_ERR_INVALID;
     if (g->n[d] < 1) return MPOIS_ERR_INVALID;
-    if (b0 == MPOIS_NEUMANN && g->grid[d] == MPOIS_VERTEX && g->n[d] < 2) return MPOIS_ERR_INVALID;
-    if (b0 != b1) return MPOIS_ERR_UNSUPPORTED;  // mixed Dirichlet/Neumann on one axis
+    if (b0 == MPOIS_NEUMANN && b1 == MPOIS_NEUMANN && g->grid[d] == MPOIS_VERTEX && g->n[d] < 2)
+      return MPOIS_ERR_INVALID;
     if (g->n[d] > (1 << 20)) return MPOIS_ERR_UNSUPPORTED;
     total *= g->n[d];
     if (total > (int64_t(1) << 34)) return MPOIS_ERR_UNSUPPORTED;
   }
+  if (!(std::isfinite(g->shift) && g->shift >= 0.0)) return MPOIS_ERR_INVALID;
   if (prec == MPOIS_F32_REFINE) {
     if (approx == MPOIS_SPECTRAL) return MPOIS_ERR_UNSUPPORTED;
     if (max_iter < 1 || max_iter > 64) return MPOIS_ERR_INVALID;
   }
   // every axis must fit one of the kernel shapes
   for (int d = 0; d < g->ndim; ++d) {
-    AxisShape s = plan_axis_shape(g->bc[d][0], g->grid[d], g->n[d], prec == MPOIS_F64);
+    AxisShape s = plan_axis_shape(axis_code(g->bc[d][0], g->bc[d][1]), g->grid[d], g->n[d], prec == MPOIS_F64);
     if (default_cfg(prec == MPOIS_F64, int(g->n[d]), int(s.P), has_rader(s), has_odd_large(s)) < 0)
       return MPOIS_ERR_UNSUPPORTED;
   }
@@ -660,7 +705,8 @@ mpois_status upload_lam(mpois_plan_s* pl, DevBuf* b, const std::vector<double>& 
 }
 
 std::string shape_key(int bc, int grid, int64_t n, const AxisShape& sh) {
-  std::string k = std::to_string(bc * 2 + (bc == MPOIS_PERIODIC ? 0 : grid)) + "/" + std::to_string(n) + "/" +
+  std::string k = std::to_string(bc * 2 + (bc == MPOIS_PERIODIC ? 0 : grid)) + "/" + std::to_string(sh.kind_f) + "." +
+                  std::to_string(sh.kind_b) + "/" + std::to_string(n) + "/" +
                   std::to_string(sh.P) + (sh.bluestein ? "b" : "e");
   for (int r : sh.radices) k += "." + std::to_string(r);
   return k;
@@ -752,28 +798,39 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
     const int e = 3 - D + d;
     sp->n[e] = g->n[d];
     sp->h[e] = g->h[d];
-    sp->bc[e] = g->bc[d][0];
+    sp->bc[e] = axis_code(g->bc[d][0], g->bc[d][1]);
+    sp->face[e][0] = g->bc[d][0];
+    sp->face[e][1] = g->bc[d][1];
     sp->grid[e] = g->bc[d][0] == MPOIS_PERIODIC ? MPOIS_VERTEX : g->grid[d];
   }
   sp->npts = sp->n[0] * sp->n[1] * sp->n[2];
-  sp->singular = true;
-  for (int d = 0; d < D; ++d)
-    if (g->bc[d][0] == MPOIS_DIRICHLET) sp->singular = false;
+  // singular: no shift and every axis periodic or Neumann on both faces
+  sp->singular = g->shift == 0.0;
+  for (int d = 0; d < D; ++d) {
+    const int code = axis_code(g->bc[d][0], g->bc[d][1]);
+    if (code != MPOIS_PERIODIC && code != MPOIS_NEUMANN) sp->singular = false;
+  }
   // weights sum
   double wsum = 1.0;
   for (int d = 0; d < D; ++d) {
     const int64_t n = g->n[d];
-    wsum *= (g->bc[d][0] == MPOIS_NEUMANN && g->grid[d] == MPOIS_VERTEX) ? double(n - 1) : double(n);
+    wsum *= (g->bc[d][0] == MPOIS_NEUMANN && g->bc[d][1] == MPOIS_NEUMANN && g->grid[d] == MPOIS_VERTEX)
+                ? double(n - 1)
+                : double(n);
   }
   sp->wsum = wsum;
   // tables, eigenvalues scaled by the product of the backward normalisations
   double c = 1.0;
-  for (int d = 0; d < D; ++d) c *= axis_norm(g->bc[d][0], g->grid[d], g->n[d]);
+  for (int d = 0; d < D; ++d) c *= axis_norm(axis_code(g->bc[d][0], g->bc[d][1]), g->grid[d], g->n[d]);
   mpois_status st = MPOIS_OK;
   sp->lam.resize(D);
   for (int d = 0; d < D; ++d) {
     std::vector<double> lam(static_cast<size_t>(g->n[d]));
-    axis_eigs(g->bc[d][0], g->grid[d], pl->approx, g->n[d], g->h[d], lam.data());
+    axis_eigs(axis_code(g->bc[d][0], g->bc[d][1]), g->grid[d], pl->approx, g->n[d], g->h[d], lam.data());
+    // the Helmholtz shift joins the divisor through axis 0's table, which
+    // every divisor contains: (sum_d lambda_d - sigma) / c
+    if (d == 0)
+      for (auto& v : lam) v -= g->shift;
     for (auto& v : lam) v /= c;
     st = pl->f64work ? upload_lam<double>(pl, &sp->lam[d], lam) : upload_lam<float>(pl, &sp->lam[d], lam);
     if (st != MPOIS_OK) return st;
@@ -781,7 +838,7 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
   // passes (input and output pointers are filled at execute time)
   auto axis_pass = [&](int d, bool fused, bool inverse) {
     Pass p;
-    const int bc = g->bc[d][0], grd = g->grid[d];
+    const int bc = axis_code(g->bc[d][0], g->bc[d][1]), grd = g->grid[d];
     const int64_t n = g->n[d];
     const AxisShape shape = plan_axis_shape(bc, grd, n, pl->f64work);
     PassArgs& a = p.args;
@@ -835,9 +892,11 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
   for (int e = 0; e < 3; ++e) {
     r.n[e] = sp->n[e];
     const bool real_axis = e >= 3 - D;
-    r.clo[e] = real_axis ? closure_of(sp->bc[e], sp->grid[e]) : C_NONE;
+    r.clo[e] = r.chi[e] = C_NONE;
+    if (real_axis) axis_closures(sp->face[e][0], sp->face[e][1], sp->grid[e], sp->n[e], &r.clo[e], &r.chi[e]);
     r.inv_h2[e] = real_axis ? 1.0 / (sp->h[e] * sp->h[e]) : 0.0;
   }
+  r.shift = g->shift;
   return MPOIS_OK;
 }
 
@@ -1197,7 +1256,7 @@ mpois_status mpois_validate(const mpois_grid_desc* grid, int approx, int prec, i
 }
 
 mpois_status mpois_axis_eigenvalues(int bc, int grid, int approx, int64_t n, double h, double* out) {
-  if (!out || n < 1 || bc < 0 || bc > 2 || (grid != 0 && grid != 1) || !(h > 0 && std::isfinite(h)))
+  if (!out || n < 1 || bc < 0 || bc > MPOIS_AXIS_ND || (grid != 0 && grid != 1) || !(h > 0 && std::isfinite(h)))
     return MPOIS_ERR_INVALID;
   if (approx != MPOIS_SPECTRAL && approx != MPOIS_FD2) return MPOIS_ERR_INVALID;
   if (bc == MPOIS_NEUMANN && grid == MPOIS_VERTEX && n < 2) return MPOIS_ERR_INVALID;
@@ -1207,7 +1266,7 @@ mpois_status mpois_axis_eigenvalues(int bc, int grid, int approx, int64_t n, dou
 
 mpois_status mpois_axis_plan(int bc, int grid, int64_t n, int* kind_fwd, int* kind_bwd, int* M, int* P, int* radices,
                              int cap, int* nradix) {
-  if (n < 1 || bc < 0 || bc > 2 || (grid != 0 && grid != 1)) return MPOIS_ERR_INVALID;
+  if (n < 1 || bc < 0 || bc > MPOIS_AXIS_ND || (grid != 0 && grid != 1)) return MPOIS_ERR_INVALID;
   if (bc == MPOIS_NEUMANN && grid == MPOIS_VERTEX && n < 2) return MPOIS_ERR_INVALID;
   AxisShape s = plan_axis_shape(bc, bc == MPOIS_PERIODIC ? MPOIS_VERTEX : grid, n, true);
   if (kind_fwd) *kind_fwd = s.kind_f;

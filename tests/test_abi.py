@@ -64,8 +64,16 @@ def test_validation(mp):
         assert lib.mpois_validate(ctypes.byref(d), 1, 0, 1) == 1
     half_periodic = _desc(mp, (4,), [("P", "D")], ("v",))
     assert lib.mpois_validate(ctypes.byref(half_periodic), 1, 0, 1) == 1
-    mixed_dn = _desc(mp, (4,), [("D", "N")], ("v",))
-    assert lib.mpois_validate(ctypes.byref(mixed_dn), 1, 0, 1) == 2
+    # different Dirichlet / Neumann faces on one axis, on either grid, any n >= 1
+    for faces in (("D", "N"), ("N", "D")):
+        for grid in ("v", "s"):
+            for n in (1, 2, 9):
+                mixed = _desc(mp, (n,), [faces], (grid,))
+                assert lib.mpois_validate(ctypes.byref(mixed), 1, 0, 1) == 0, (faces, grid, n)
+    # Helmholtz shift: finite and >= 0
+    for sig, want in ((0.0, 0), (2.5, 0), (-1.0, 1), (float("nan"), 1), (float("inf"), 1)):
+        d = mp.make_desc((8, 8), (0.1, 0.1), ("N", "P"), ("v", "v"), shift=sig)
+        assert lib.mpois_validate(ctypes.byref(d), 1, 0, 1) == want, sig
     # spectral with refinement is not provided
     assert lib.mpois_validate(ctypes.byref(ok), 0, 2, 1) == 2
     assert lib.mpois_validate(ctypes.byref(ok), 1, 2, 0) == 1
@@ -90,7 +98,8 @@ def test_plan_without_device_reports_device_error(mp):
     assert not h.value
 
 
-@pytest.mark.parametrize("bc,grid", [("P", "v"), ("D", "v"), ("D", "s"), ("N", "v"), ("N", "s")])
+@pytest.mark.parametrize("bc,grid", [("P", "v"), ("D", "v"), ("D", "s"), ("N", "v"), ("N", "s"),
+                                     ("DN", "v"), ("DN", "s"), ("ND", "v"), ("ND", "s")])
 @pytest.mark.parametrize("approx", ["fd", "ps"])
 def test_axis_eigenvalues_match_oracle(mp, bc, grid, approx):
     for n in (2, 3, 7, 16, 33, 511, 512, 1021):
@@ -114,6 +123,15 @@ def test_axis_plans(mp):
     assert p["M"] == 2050 and p["P"] >= 4099 and set(p["radices"]) <= {2, 4, 8, 16, 3, 9, 5, 7, 11, 13}
     p = mp.axis_plan("N", "v", 512)  # 1022 = 73 * 14: Rader stage, then one radix-14 stage
     assert p["P"] == 1022 and list(p["radices"]) == [73, 14]
+    # mixed faces: vertex DST-III/II and DCT-III/II of length n, staggered type IV of length 2n
+    p = mp.axis_plan("DN", "v", 64)
+    assert (p["forward"], p["backward"], p["M"]) == ("DST-III", "DST-II", 64)
+    p = mp.axis_plan("ND", "v", 64)
+    assert (p["forward"], p["backward"], p["M"]) == ("DCT-III", "DCT-II", 64)
+    p = mp.axis_plan("DN", "s", 100)
+    assert (p["forward"], p["backward"], p["M"]) == ("DST-IV", "DST-IV", 200)
+    p = mp.axis_plan("ND", "s", 100)
+    assert (p["forward"], p["backward"], p["M"]) == ("DCT-IV", "DCT-IV", 200)
     for n in range(1, 300):
         for bc, grid in (("P", "v"), ("N", "s"), ("D", "v"), ("N", "v")):
             if (bc, grid) == ("N", "v") and n < 2:

@@ -39,9 +39,10 @@ def rel_err(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def gpu_solve(g, shape, h, bc, grid, approx, prec, max_iter=2, graph=False, tune=False):
+def gpu_solve(g, shape, h, bc, grid, approx, prec, max_iter=2, graph=False, tune=False, shift=0.0):
     mp = _mp()
-    plan = mp.Plan(shape, h, bc, grid, approx=approx, prec=prec, max_iter=max_iter, graph=graph, tune=tune)
+    plan = mp.Plan(shape, h, bc, grid, approx=approx, prec=prec, max_iter=max_iter, graph=graph, tune=tune,
+                   shift=shift)
     dt = torch.float32 if prec == "f32" else torch.float64
     rhs = torch.as_tensor(np.ascontiguousarray(g), dtype=dt).cuda()
     phi = torch.empty_like(rhs)
@@ -53,19 +54,19 @@ def gpu_solve(g, shape, h, bc, grid, approx, prec, max_iter=2, graph=False, tune
     return out, info
 
 
-def oracle_solve(g, shape, h, bc, grid, approx):
+def oracle_solve(g, shape, h, bc, grid, approx, shift=0.0):
     axes = oracle.axes_from(shape, h, bc, grid)
-    return oracle.solve(g, axes, approx)
+    return oracle.solve(g, axes, approx, shift=shift)
 
 
-def check(shape, kinds, approx, prec, seed=0, h=None, max_iter=2):
+def check(shape, kinds, approx, prec, seed=0, h=None, max_iter=2, shift=0.0):
     bc = tuple(k[0] for k in kinds)
     grid = tuple(k[1] for k in kinds)
     h = h or tuple(1.0 / (n + 1) for n in shape)
-    print(f"[parity] shape={shape} kinds={kinds} approx={approx} prec={prec} seed={seed}", flush=True)
+    print(f"[parity] shape={shape} kinds={kinds} approx={approx} prec={prec} seed={seed} shift={shift}", flush=True)
     g = np.random.default_rng(seed).standard_normal(shape)
-    ref = oracle_solve(g, shape, h, bc, grid, approx)
-    out, info = gpu_solve(g, shape, h, bc, grid, approx, prec, max_iter=max_iter)
+    ref = oracle_solve(g, shape, h, bc, grid, approx, shift)
+    out, info = gpu_solve(g, shape, h, bc, grid, approx, prec, max_iter=max_iter, shift=shift)
     err = rel_err(out, ref)
     assert err <= TOL[prec], (shape, kinds, approx, prec, err)
     return err, info
@@ -367,3 +368,65 @@ def test_specialised_kernels_match_generic_and_oracle(prec, monkeypatch):
         assert rel_err(out_s, out_g) <= (1e-5 if prec == "f32" else 1e-13), (shape, prec)
         ref = oracle_solve(g, shape, h, bc, grid, "fd")
         assert rel_err(out_s, ref) <= TOL[prec], (shape, prec)
+
+
+
+# ------------------------------------------------------------------ different faces on one axis, Helmholtz shift
+MIXED = [("DN", "v"), ("DN", "s"), ("ND", "v"), ("ND", "s")]
+MIXED_LENGTHS = [1, 2, 3, 4, 5, 7, 8, 12, 16, 31, 32, 37, 64, 100, 127, 128, 255, 256, 257, 511, 512, 1000, 1024]
+
+
+@pytest.mark.parametrize("kind", MIXED)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_1d_mixed_faces_all_lengths(kind, prec):
+    """Dirichlet on one face and Neumann on the other: vertex DST-III/II and DCT-III/II,
+    staggered DST-IV / DCT-IV (length-2n DFT of the modulated pair), FD and PS."""
+    for n in MIXED_LENGTHS:
+        for approx in ("fd", "ps"):
+            check((n,), [kind], approx, prec, seed=n + 3)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32r"])
+def test_mixed_faces_2d_3d(prec):
+    for k0, k1 in itertools.product(MIXED + [("P", "v"), ("N", "s")], repeat=2):
+        check((21, 34), [k0, k1], "fd", prec, seed=5)
+    for kinds in ([("DN", "s"), ("P", "v"), ("ND", "v")], [("ND", "s")] * 3, [("N", "v"), ("DN", "v"), ("D", "s")]):
+        check((19, 24, 35), kinds, "fd", prec, seed=6)
+        if prec != "f32r":
+            check((19, 24, 35), kinds, "ps", prec, seed=6)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32r"])
+def test_helmholtz_shift(prec):
+    """(Lap - sigma) phi = g: the shift joins the eigenvalue divisor (and the FP64
+    residual of refinement); with sigma > 0 periodic / Neumann problems are not singular."""
+    for kinds in ([("P", "v")] * 3, [("N", "v"), ("N", "s"), ("P", "v")], [("D", "s"), ("DN", "v"), ("N", "s")]):
+        for shift in (0.5, 40.0):
+            check((18, 23, 30), kinds, "fd", prec, seed=8, shift=shift)
+            if prec != "f32r":
+                check((18, 23, 30), kinds, "ps", prec, seed=9, shift=shift)
+    # 512-point DCT-I axes (the specialised kernels) with a shift
+    check((512, 6, 512), [("N", "v")] * 3, "fd", prec, seed=10, shift=3.0, h=(1 / 511,) * 3)
+
+
+def test_batch_mixed_faces_and_shift():
+    """Batch entries with mixed faces and their own shifts, FP32 + refinement."""
+    rng = np.random.default_rng(12)
+    descs = []
+    for i in range(16):
+        n0, n1 = int(rng.integers(8, 120)), int(rng.integers(8, 120))
+        k0 = MIXED[i % 4]
+        k1 = [("P", "v"), ("N", "s"), ("D", "v"), ("ND", "s")][i % 4]
+        descs.append({"shape": (n0, n1), "h": (1.0 / n0, 1.0 / n1), "bc": (k0[0], k1[0]),
+                      "grid": (k0[1], k1[1]), "approx": "fd", "shift": float(i % 3) * 2.0})
+    mp = _mp()
+    rhs = [torch.as_tensor(np.random.default_rng([12, i]).standard_normal(d["shape"])).cuda() for i, d in enumerate(descs)]
+    phi = [torch.empty_like(r) for r in rhs]
+    plan = mp.BatchPlan(descs, prec="f32r", max_iter=2)
+    plan.solve(rhs, phi)
+    torch.cuda.synchronize()
+    for i, d in enumerate(descs):
+        ref = oracle_solve(rhs[i].cpu().numpy(), d["shape"], d["h"], d["bc"], d["grid"], "fd", d["shift"])
+        assert rel_err(phi[i].cpu().numpy(), ref) <= 1e-12, (i, d)
+    assert plan.info()["rel_resid"] < 1e-11
+    plan.close()
