@@ -125,6 +125,21 @@ mpois_status mpois_plan_create_batch(const mpois_grid_desc* grids, int count, in
  * elsewhere) and has zero weighted mean. */
 mpois_status mpois_execute(mpois_plan plan, const void* rhs, void* phi, void* stream);
 
+/* Solve for arrays that are views into larger arrays, e.g. the interior of a
+ * halo-padded CFD field (Section 3: the right-hand side and the solution may
+ * be a subset of a larger array with ghost cells).  rhs / phi point at element
+ * (0, .., 0) of the grid; rhs_strides / phi_strides give ndim element strides,
+ * row-major-like and non-overlapping: strides[ndim-1] >= 1 and strides[d] >=
+ * strides[d+1] * n[d+1].  The views are read and written in place by the
+ * first, last (and, for MPOIS_F64 / MPOIS_F32, every) sweep and by the
+ * refinement residual; elements outside them are never touched.  rhs == phi
+ * with equal strides is allowed except with MPOIS_F32_REFINE; overlapping
+ * views otherwise are INVALID, as are bad strides.  Always enqueued eagerly
+ * (the graph and profiling flags apply to mpois_execute).  mpois_get_info
+ * reports on the views. */
+mpois_status mpois_execute_view(mpois_plan plan, const void* rhs, const int64_t* rhs_strides, void* phi,
+                                const int64_t* phi_strides, void* stream);
+
 /* Largest scratch the allocation-free execute uses (bytes per device). */
 #define MPOIS_NOALLOC_SCRATCH_BYTES (65u << 20)
 

@@ -74,6 +74,7 @@ def load_library():
     lib.mpois_execute.argtypes = [P, P, P, P]
     lib.mpois_execute_batch.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
     lib.mpois_execute_noalloc.argtypes = [P, P, P, P]
+    lib.mpois_execute_view.argtypes = [P, P, ctypes.POINTER(ctypes.c_int64), P, ctypes.POINTER(ctypes.c_int64), P]
     lib.mpois_get_info.argtypes = [P, P, ctypes.POINTER(Info)]
     lib.mpois_destroy.argtypes = [P]
     lib.mpois_workspace_bytes.argtypes = [P]
@@ -89,7 +90,7 @@ def load_library():
         [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.mpois_kernel_shape.argtypes = [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
     for name in ("mpois_kernel_shape", "mpois_plan_create", "mpois_plan_create_batch", "mpois_execute", "mpois_execute_batch",
-                 "mpois_execute_noalloc",
+                 "mpois_execute_noalloc", "mpois_execute_view",
                  "mpois_get_info", "mpois_destroy", "mpois_validate", "mpois_axis_eigenvalues", "mpois_axis_plan",
                  "mpois_profile"):
         getattr(lib, name).restype = ctypes.c_int
@@ -218,6 +219,24 @@ class Plan:
                                     _stream_ptr(stream))
         if st:
             raise MpoisError(st, "mpois_execute")
+        return phi
+
+    def solve_view(self, rhs, phi, stream=None):
+        """mpois_execute_view: rhs and phi may be strided views (e.g. the interior
+        of halo-padded tensors, t[1:-1, 1:-1]) of this plan's shape and dtype."""
+        import torch
+        for t, what in ((rhs, "rhs"), (phi, "phi")):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != self.dtype:
+                raise TypeError(f"{what} must be a CUDA (HIP) tensor of {self.dtype}")
+            if tuple(t.shape) != self.shape:
+                raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {self.shape}")
+        nd = len(self.shape)
+        rs = (ctypes.c_int64 * nd)(*rhs.stride())
+        ps = (ctypes.c_int64 * nd)(*phi.stride())
+        st = self.lib.mpois_execute_view(self._h, ctypes.c_void_p(rhs.data_ptr()), rs, ctypes.c_void_p(phi.data_ptr()),
+                                         ps, _stream_ptr(stream))
+        if st:
+            raise MpoisError(st, "mpois_execute_view")
         return phi
 
     def solve_noalloc(self, rhs, phi, stream=None):

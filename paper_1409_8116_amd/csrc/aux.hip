@@ -125,13 +125,13 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
       const int64_t i1 = rem / strips;
       const int64_t i2 = (rem - i1 * strips) * RESID_NT + threadIdx.x;
       if (i2 >= n2) continue;
-      const int64_t base = i1 * n2 + i2;
+      const int64_t gbase = i1 * a.gs[1] + i2 * a.gs[2];
       const double w12 = axis_weight(a.clo[1], a.chi[1], i1, n1) * axis_weight(a.clo[2], a.chi[2], i2, n2);
       const int64_t s0 = seg * RESID_SEG;
       const int64_t s1 = (s0 + RESID_SEG < n0) ? s0 + RESID_SEG : n0;
 #pragma unroll 4
       for (int64_t i0 = s0; i0 < s1; ++i0) {
-        const double gv = a.g[i0 * plane + base];
+        const double gv = a.g[i0 * a.gs[0] + gbase];
         const double gc = gv - mg;
         s_wg += w12 * axis_weight(a.clo[0], a.chi[0], i0, n0) * gv;
         s_g2 += gc * gc;
@@ -149,24 +149,27 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
     const int64_t i1 = rem / strips;
     const int64_t i2 = (rem - i1 * strips) * RESID_NT + threadIdx.x;
     if (i2 >= n2) continue;
+    // phi and g may be views into larger (halo-padded) arrays: their own
+    // strides; r is C-contiguous
+    const int64_t p0 = a.ps[0], g0 = a.gs[0];
     const int64_t base = i1 * n2 + i2;
     const double w12 = axis_weight(a.clo[1], a.chi[1], i1, n1) * axis_weight(a.clo[2], a.chi[2], i2, n2);
     // axes 2 and 1: neighbour offsets and weights are fixed for this thread
-    const Neighbours q2 = neighbours(i2, n2, 1, a.clo[2], a.chi[2]);
-    const Neighbours q1 = neighbours(i1, n1, n2, a.clo[1], a.chi[1]);
-    const double* __restrict__ pp = phi + base;
-    const double* __restrict__ gp = g + base;
+    const Neighbours q2 = neighbours(i2, n2, a.ps[2], a.clo[2], a.chi[2]);
+    const Neighbours q1 = neighbours(i1, n1, a.ps[1], a.clo[1], a.chi[1]);
+    const double* __restrict__ pp = phi + i1 * a.ps[1] + i2 * a.ps[2];
+    const double* __restrict__ gp = g + i1 * a.gs[1] + i2 * a.gs[2];
     const double first = pp[0];
-    const double last = pp[(n0 - 1) * plane];
+    const double last = pp[(n0 - 1) * p0];
     const int64_t s0 = seg * RESID_SEG;
     const int64_t s1 = (s0 + RESID_SEG < n0) ? s0 + RESID_SEG : n0;
-    double prev = s0 > 0 ? pp[(s0 - 1) * plane] : 0.0;
-    double cur = pp[s0 * plane];
-    double next = s0 + 1 < n0 ? pp[(s0 + 1) * plane] : cur;
-    int64_t o = s0 * plane;
+    double prev = s0 > 0 ? pp[(s0 - 1) * p0] : 0.0;
+    double cur = pp[s0 * p0];
+    double next = s0 + 1 < n0 ? pp[(s0 + 1) * p0] : cur;
+    int64_t o = s0 * p0, og = s0 * g0, orr = s0 * plane;
 #pragma unroll 4
-    for (int64_t i0 = s0; i0 < s1; ++i0, o += plane) {
-      const double gv = gp[o];
+    for (int64_t i0 = s0; i0 < s1; ++i0, o += p0, og += g0, orr += plane) {
+      const double gv = gp[og];
       const double d2 = q2.alo * pp[o + q2.dlo] + q2.blo * cur - 2.0 * cur + q2.ahi * pp[o + q2.dhi] + q2.bhi * cur;
       const double d1 = q1.alo * pp[o + q1.dlo] + q1.blo * cur - 2.0 * cur + q1.ahi * pp[o + q1.dhi] + q1.bhi * cur;
       const double lap = a.inv_h2[2] * d2 + a.inv_h2[1] * d1 +
@@ -174,8 +177,8 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
                          a.shift * cur;
       const double gc = gv - mg;
       const double r = gc - lap;
-      if (r64) r64[base + o] = r;
-      else if (r32) r32[base + o] = float(r);
+      if (r64) r64[base + orr] = r;
+      else if (r32) r32[base + orr] = float(r);
       const double w = w12 * axis_weight(a.clo[0], a.chi[0], i0, n0);
       s_wphi += w * cur;
       s_wg += w * gv;
@@ -183,7 +186,7 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
       s_g2 += gc * gc;
       prev = cur;
       cur = next;
-      next = (i0 + 2 < n0) ? pp[o + 2 * plane] : cur;
+      next = (i0 + 2 < n0) ? pp[o + 2 * p0] : cur;
     }
   }
   __shared__ double red[4][RESID_NT];

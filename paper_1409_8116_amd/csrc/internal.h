@@ -65,6 +65,14 @@ struct PassArgs {
   const void* lam_b;
   int64_t nb;           // length of the axis behind lam_b
   AxisDev ax;
+  // Element addressing of src and dst: element j of line l sits at
+  // (l / vnb) * va + (l % vnb) * vb + j * vd.  A C-contiguous array has
+  // vnb = inner, va = n * inner, vb = 1, vd = inner; a view into a larger
+  // (halo-padded) array has the strides of that array.  contig: both are
+  // C-contiguous (the specialised tile paths need it).
+  int64_t src_vnb, src_va, src_vb, src_vd;
+  int64_t dst_vnb, dst_va, dst_vb, dst_vd;
+  int contig;
 };
 
 // One launch of the line-transform kernel over many grids.
@@ -88,6 +96,8 @@ struct ResidArgs {
   void* r;              // output residual (or null), float or double
   int r_f64;
   int64_t n[3];
+  int64_t ps[3];        // element strides of phi per axis (C-contiguous: n1 n2, n2, 1)
+  int64_t gs[3];        // element strides of g (r is always C-contiguous)
   int clo[3];           // closure at the low end of each axis
   int chi[3];           // closure at the high end
   double inv_h2[3];

@@ -1200,7 +1200,7 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
   int mode = 0;       // 0 generic, 1 contiguous fast path, 2 strided fast path
   int64_t tbase = 0;  // element offset of the tile's first element
   if constexpr (kFast) {
-    const bool full = l0 + TL <= a.nlines;
+    const bool full = l0 + TL <= a.nlines && a.contig;
     constexpr int64_t kLim = int64_t(1) << 29;  // elements: byte offsets of 8-byte values stay below 2^32
     if (B == 1) {
       mode = (full && int64_t(TL) * n < kLim) ? 1 : 0;
@@ -1245,13 +1245,14 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
     const int t = tid % TL;
     const int64_t l = l0 + t;
     const bool ok = l < a.nlines;
-    const int64_t base = ok ? (l / B) * (int64_t(n) * B) + (l % B) : 0;
+    const int64_t base = ok ? (l / a.src_vnb) * a.src_va + (l % a.src_vnb) * a.src_vb : 0;
+    const int64_t sd = a.src_vd;
     for (int c = 0; c < ELD && c * (NT / TL) < n; c += CH) {
       S ld[CH];
 #pragma unroll
       for (int i = 0; i < CH; ++i) {
         const int j = tid / TL + (c + i) * (NT / TL);
-        ld[i] = src[(ok && j < n) ? base + int64_t(j) * B : 0];
+        ld[i] = src[(ok && j < n) ? base + int64_t(j) * sd : base];
       }
 #pragma unroll
       for (int i = 0; i < CH; ++i) {
@@ -1343,14 +1344,15 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
     const int t = tid % TL;
     const int64_t l = l0 + t;
     if (l >= a.nlines) return;
-    const int64_t base = (l / B) * (int64_t(n) * B) + (l % B);
+    const int64_t base = (l / a.dst_vnb) * a.dst_va + (l % a.dst_vnb) * a.dst_vb;
+    const int64_t sd = a.dst_vd;
     for (int c = 0; c < ELD && c * (NT / TL) < n; c += CH) {
       D old[CH];
       if (update) {
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
           const int j = tid / TL + (c + i) * (NT / TL);
-          old[i] = dst[j < n ? base + int64_t(j) * B : base];
+          old[i] = dst[j < n ? base + int64_t(j) * sd : base];
         }
       }
 #pragma unroll
@@ -1358,7 +1360,7 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
         const int j = tid / TL + (c + i) * (NT / TL);
         if (j < n) {
           const T x = X[j * XP + t];
-          dst[base + int64_t(j) * B] = update ? D(double(old[i]) + double(x) - shift) : D(x);
+          dst[base + int64_t(j) * sd] = update ? D(double(old[i]) + double(x) - shift) : D(x);
         }
       }
     }

@@ -410,6 +410,9 @@ struct mpois_plan_s {
   void* last_phi = nullptr;
   const void* checked_rhs = nullptr;  // last pointer pair that passed check_ptrs
   void* checked_phi = nullptr;
+  int64_t last_rhs_view[3] = {0, 0, 0};  // padded strides of the last execute's arrays
+  int64_t last_phi_view[3] = {0, 0, 0};
+  bool last_view = false;                 // the last execute used views
   std::vector<const void*> last_rhs_b;
   std::vector<void*> last_phi_b;
   int last_iters = 0;
@@ -871,6 +874,12 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
       p.cfg = default_cfg(pl->f64work, int(n), int(shape.P), has_rader(shape), has_odd_large(shape));
     }
     a.ax = pl->tables[ti].dev;
+    // C-contiguous addressing of src and dst (views override it per execute)
+    a.src_vnb = a.dst_vnb = inner;
+    a.src_va = a.dst_va = n * inner;
+    a.src_vb = a.dst_vb = 1;
+    a.src_vd = a.dst_vd = inner;
+    a.contig = 1;
     // a kernel compiled for exactly this transform, unless switched off
     // (MPOIS_NO_SPEC=1, a test hook comparing it with the generic shapes)
     const char* nospec = std::getenv("MPOIS_NO_SPEC");
@@ -891,6 +900,7 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
   ResidArgs& r = sp->resid;
   for (int e = 0; e < 3; ++e) {
     r.n[e] = sp->n[e];
+    r.ps[e] = r.gs[e] = (e == 0 ? sp->n[1] * sp->n[2] : e == 1 ? sp->n[2] : 1);
     const bool real_axis = e >= 3 - D;
     r.clo[e] = r.chi[e] = C_NONE;
     if (real_axis) axis_closures(sp->face[e][0], sp->face[e][1], sp->grid[e], sp->n[e], &r.clo[e], &r.chi[e]);
@@ -1000,8 +1010,27 @@ void prof_mark(mpois_plan_s* pl, int kernel, double bytes, hipStream_t s) {
   (void)hipEventRecord(r.end, s);
 }
 
+// Element strides of the caller's arrays, padded to 3D (leading unit axes), or
+// null for C-contiguous arrays.
+struct IoViews {
+  const int64_t* rhs = nullptr;
+  const int64_t* phi = nullptr;
+};
+
+// Addressing of one array in a pass along padded axis `ax`: lines enumerate
+// the other two axes (oa outer, ob inner).
+void set_view(int ax, const int64_t n[3], const int64_t st[3], int64_t* vnb, int64_t* va, int64_t* vb, int64_t* vd) {
+  const int oa = ax == 0 ? 1 : 0, ob = ax == 2 ? 1 : 2;
+  *vnb = n[ob];
+  *va = st[oa];
+  *vb = st[ob];
+  *vd = st[ax];
+}
+
 hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, void* out, int out_f64, void* work,
-                     int work_f64, bool update, const double* shift, hipStream_t s) {
+                     int work_f64, bool update, const double* shift, hipStream_t s,
+                     const int64_t* in_view = nullptr, const int64_t* out_view = nullptr,
+                     const int64_t* work_view = nullptr) {
   const size_t np = sp.passes.size();
   for (size_t i = 0; i < np; ++i) {
     Pass& p = sp.passes[i];
@@ -1011,8 +1040,16 @@ hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, 
     const bool last = i + 1 == np;
     a.dst = last ? out : work;
     a.dst_f64 = last ? out_f64 : work_f64;
+    const int64_t* sv = i == 0 ? in_view : work_view;
+    const int64_t* dv = last ? out_view : work_view;
+    const int axp = 3 - sp.ndim + p.axis;
+    if (sv) set_view(axp, sp.n, sv, &a.src_vnb, &a.src_va, &a.src_vb, &a.src_vd);
+    if (dv) set_view(axp, sp.n, dv, &a.dst_vnb, &a.dst_va, &a.dst_vb, &a.dst_vd);
+    a.contig = (sv || dv) ? 0 : 1;
     a.update = (last && update) ? 1 : 0;
     a.shift = shift;
+    // the specialised kernels take the contiguous tile paths when they can, and
+    // their generic path otherwise (views included)
     hipError_t e = p.spec >= 0 ? launch_spec(p.spec, a, s) : launch_line_pass(p.cfg, a, s);
     if (e != hipSuccess) return e;
     const double pts = double(sp.npts);
@@ -1035,8 +1072,13 @@ Workspace plan_workspace(mpois_plan_s* pl) {
 }
 
 hipError_t run_resid(mpois_plan_s* pl, SubPlan& sp, const void* rhs, const void* phi, void* r, int r_f64,
-                     const double* mg, double* scalars, hipStream_t s, double* partials = nullptr) {
+                     const double* mg, double* scalars, hipStream_t s, double* partials = nullptr,
+                     const IoViews& views = IoViews()) {
   ResidArgs a = sp.resid;
+  for (int e = 0; e < 3; ++e) {
+    if (views.phi) a.ps[e] = views.phi[e];
+    if (views.rhs) a.gs[e] = views.rhs[e];
+  }
   a.phi = static_cast<const double*>(phi);
   a.g = static_cast<const double*>(rhs);
   a.r = r;
@@ -1053,25 +1095,28 @@ hipError_t run_resid(mpois_plan_s* pl, SubPlan& sp, const void* rhs, const void*
 }
 
 hipError_t enqueue_one(mpois_plan_s* pl, SubPlan& sp, size_t sub_index, const void* rhs, void* phi, hipStream_t s,
-                       const Workspace& ws) {
-  if (pl->prec == MPOIS_F64) return run_solve(pl, sp, rhs, 1, phi, 1, phi, 1, false, nullptr, s);
-  if (pl->prec == MPOIS_F32) return run_solve(pl, sp, rhs, 0, phi, 0, phi, 0, false, nullptr, s);
+                       const Workspace& ws, const IoViews& v = IoViews()) {
+  // F64 / F32: every sweep works in place on phi (through its view)
+  if (pl->prec == MPOIS_F64) return run_solve(pl, sp, rhs, 1, phi, 1, phi, 1, false, nullptr, s, v.rhs, v.phi, v.phi);
+  if (pl->prec == MPOIS_F32) return run_solve(pl, sp, rhs, 0, phi, 0, phi, 0, false, nullptr, s, v.rhs, v.phi, v.phi);
   // FP32 solve, then fixed number of FP64-residual corrections.
   double* sc = ws.scalars + sub_index * S_COUNT;
   void* work = ws.work;
   hipError_t e;
   if (sp.singular) {
     // m_g = sum w g / sum w, so the FP32 residual carries no large constant.
-    if ((e = run_resid(pl, sp, rhs, nullptr, nullptr, 0, nullptr, sc, s, ws.partials)) != hipSuccess) return e;
+    if ((e = run_resid(pl, sp, rhs, nullptr, nullptr, 0, nullptr, sc, s, ws.partials, v)) != hipSuccess) return e;
   }
-  if ((e = run_solve(pl, sp, rhs, 1, phi, 1, work, 0, false, nullptr, s)) != hipSuccess) return e;
+  if ((e = run_solve(pl, sp, rhs, 1, phi, 1, work, 0, false, nullptr, s, v.rhs, v.phi, nullptr)) != hipSuccess)
+    return e;
   for (int it = 0; it < pl->max_iter; ++it) {
     // r = g - m_g - L phi (FP64, stored FP32), sum w phi -> gauge shift
-    if ((e = run_resid(pl, sp, rhs, phi, work, 0, sp.singular ? sc + S_MG : nullptr, sc, s, ws.partials)) !=
+    if ((e = run_resid(pl, sp, rhs, phi, work, 0, sp.singular ? sc + S_MG : nullptr, sc, s, ws.partials, v)) !=
         hipSuccess)
       return e;
     // phi <- phi + delta, minus the weighted mean of phi when the problem is singular
-    if ((e = run_solve(pl, sp, work, 0, phi, 1, work, 0, true, sp.singular ? sc + S_SHIFT : nullptr, s)) != hipSuccess)
+    if ((e = run_solve(pl, sp, work, 0, phi, 1, work, 0, true, sp.singular ? sc + S_SHIFT : nullptr, s, nullptr, v.phi,
+                       nullptr)) != hipSuccess)
       return e;
   }
   return hipSuccess;
@@ -1320,6 +1365,7 @@ mpois_status mpois_execute(mpois_plan pl, const void* rhs, void* phi, void* stre
   hipStream_t s = static_cast<hipStream_t>(stream);
   pl->last_rhs = rhs;
   pl->last_phi = phi;
+  pl->last_view = false;
   pl->last_rhs_b.clear();
   pl->last_phi_b.clear();
   pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
@@ -1383,6 +1429,62 @@ static mpois_status batch_set_tables(mpois_plan_s* pl, const void* const* rhs, v
   return MPOIS_OK;
 }
 
+// ---------------------------------------------------------------------------- views into larger arrays
+// Checks of one view: strides of a row-major-like, non-self-overlapping layout
+// (s[d] >= s[d+1] n[d+1] >= 1); padded to 3D; extent in elements.
+static mpois_status view_strides(const SubPlan& sp, const int64_t* st, int64_t out[3], int64_t* extent) {
+  const int D = sp.ndim;
+  for (int d = 0; d < D; ++d)
+    if (st[d] < 1) return MPOIS_ERR_INVALID;
+  for (int d = 0; d + 1 < D; ++d)
+    if (st[d] < st[d + 1] * sp.n[3 - D + d + 1]) return MPOIS_ERR_INVALID;
+  int64_t ext = 1;
+  for (int e = 0; e < 3; ++e) {
+    const int d = e - (3 - D);
+    out[e] = d >= 0 ? st[d] : st[0] * sp.n[3 - D];
+    if (d >= 0) ext += (sp.n[e] - 1) * st[d];
+  }
+  *extent = ext;
+  return MPOIS_OK;
+}
+
+mpois_status mpois_execute_view(mpois_plan pl, const void* rhs, const int64_t* rhs_strides, void* phi,
+                                const int64_t* phi_strides, void* stream) {
+  if (!pl || pl->subs.size() != 1 || !rhs || !phi || !rhs_strides || !phi_strides) return MPOIS_ERR_INVALID;
+  SubPlan& sp = pl->subs[0];
+  int64_t rs[3], ps[3], rext = 0, pext = 0;
+  mpois_status st = view_strides(sp, rhs_strides, rs, &rext);
+  if (st == MPOIS_OK) st = view_strides(sp, phi_strides, ps, &pext);
+  if (st != MPOIS_OK) return st;
+  const size_t es = pl->prec == MPOIS_F32 ? 4 : 8;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(rhs), b0 = reinterpret_cast<uintptr_t>(phi);
+  const bool same = a0 == b0 && std::equal(rs, rs + 3, ps);
+  if (same && pl->prec == MPOIS_F32_REFINE) return MPOIS_ERR_INVALID;
+  if (!same && a0 < b0 + uintptr_t(pext) * es && b0 < a0 + uintptr_t(rext) * es) return MPOIS_ERR_INVALID;
+  for (const void* p : {rhs, static_cast<const void*>(phi)}) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+      (void)hipGetLastError();
+      return MPOIS_ERR_INVALID;
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) return MPOIS_ERR_INVALID;
+  }
+  pl->last_rhs = rhs;
+  pl->last_phi = phi;
+  pl->last_rhs_b.clear();
+  pl->last_phi_b.clear();
+  std::copy(rs, rs + 3, pl->last_rhs_view);
+  std::copy(ps, ps + 3, pl->last_phi_view);
+  pl->last_view = true;
+  pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
+  IoViews v;
+  v.rhs = pl->last_rhs_view;
+  v.phi = pl->last_phi_view;
+  return enqueue_one(pl, sp, 0, rhs, phi, static_cast<hipStream_t>(stream), plan_workspace(pl), v) == hipSuccess
+             ? MPOIS_OK
+             : MPOIS_ERR_DEVICE;
+}
+
 // ---------------------------------------------------------------------------- allocation-free execute
 // Static scratch of mpois_execute_noalloc: every device the library runs on
 // holds one copy until the process ends.  Layout: reduced scalars (256 B),
@@ -1440,6 +1542,7 @@ mpois_status mpois_execute_noalloc(mpois_plan pl, const void* rhs, void* phi, vo
                reinterpret_cast<double*>(b)};
   pl->last_rhs = rhs;
   pl->last_phi = phi;
+  pl->last_view = false;
   pl->last_rhs_b.clear();
   pl->last_phi_b.clear();
   pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
@@ -1460,6 +1563,7 @@ mpois_status mpois_execute_batch(mpois_plan pl, const void* const* rhs, void* co
   }
   pl->last_rhs = nullptr;
   pl->last_phi = nullptr;
+  pl->last_view = false;
   pl->last_rhs_b.assign(rhs, rhs + count);
   pl->last_phi_b.assign(phi, phi + count);
   pl->last_iters = pl->prec == MPOIS_F32_REFINE ? 1 + pl->max_iter : 1;
@@ -1498,9 +1602,14 @@ mpois_status mpois_get_info(mpois_plan pl, void* stream, mpois_info* out) {
       const void* rhs = batch ? pl->last_rhs_b[i] : pl->last_rhs;
       const void* phi = batch ? pl->last_phi_b[i] : pl->last_phi;
       double* sc = static_cast<double*>(pl->scalars.p) + i * S_COUNT;
-      if (sp.singular && run_resid(pl, sp, rhs, nullptr, nullptr, 0, nullptr, sc, s) != hipSuccess)
+      IoViews v;
+      if (!batch && pl->last_view) {
+        v.rhs = pl->last_rhs_view;
+        v.phi = pl->last_phi_view;
+      }
+      if (sp.singular && run_resid(pl, sp, rhs, nullptr, nullptr, 0, nullptr, sc, s, nullptr, v) != hipSuccess)
         return MPOIS_ERR_DEVICE;
-      if (run_resid(pl, sp, rhs, phi, nullptr, 0, sp.singular ? sc + S_MG : nullptr, sc, s) != hipSuccess)
+      if (run_resid(pl, sp, rhs, phi, nullptr, 0, sp.singular ? sc + S_MG : nullptr, sc, s, nullptr, v) != hipSuccess)
         return MPOIS_ERR_DEVICE;
       double host[S_COUNT];
       if (hipMemcpyAsync(host, sc, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess) return MPOIS_ERR_DEVICE;

@@ -1,0 +1,92 @@
+"""GPU parity of solves on views into larger arrays (ghost-cell / halo-padded
+fields): the right-hand side and the solution are strided sub-arrays; the
+interior must match the oracle and every element outside the views must be
+left as it was."""
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32r": 1e-12}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1409_8116_amd as mp
+    mp.load_library()
+    yield
+
+
+def _padded(shape, pad, dt, seed):
+    big = torch.as_tensor(np.random.default_rng(seed).standard_normal([n + 2 * p for n, p in zip(shape, pad)]),
+                          dtype=dt).cuda()
+    view = big[tuple(slice(p, p + n) for n, p in zip(shape, pad))]
+    return big, view
+
+
+CASES = [
+    ((20, 17, 26), (1, 2, 3), ("P", "D", "N"), ("v", "s", "v")),
+    ((33, 12, 40), (2, 1, 1), ("N", ("D", "N"), "P"), ("v", "v", "s")),
+    ((512, 6, 512), (1, 1, 2), ("N", "N", "N"), ("v", "v", "v")),   # specialised DCT-I kernels, generic tile path
+    ((45, 64), (3, 2), ("D", "N"), ("v", "s")),
+    ((300,), (5,), (("N", "D"),), ("s",)),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32r"])
+def test_halo_padded_views_match_oracle_and_keep_the_halo(prec):
+    import paper_1409_8116_amd as mp
+    dt = torch.float32 if prec == "f32" else torch.float64
+    for shape, pad, bc, grid in CASES:
+        print(f"[views] {prec} {shape} pad={pad} {bc} {grid}", flush=True)
+        h = tuple(1.0 / (n + 1) for n in shape)
+        g_big, g = _padded(shape, pad, dt, 1)
+        p_big, phi = _padded(shape, tuple(q + 1 for q in pad), dt, 2)  # different halo widths
+        g_before, p_before = g_big.clone(), p_big.clone()
+        plan = mp.Plan(shape, h, bc, grid, prec=prec, max_iter=2)
+        plan.solve_view(g, phi)
+        torch.cuda.synchronize()
+        ref = oracle.solve(g.double().cpu().numpy(), oracle.axes_from(shape, h, bc, grid), "fd")
+        out = phi.double().cpu().numpy()
+        err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+        assert err <= TOL[prec], (shape, prec, err)
+        assert torch.equal(g_big, g_before)  # the right-hand side is read-only
+        mask = torch.ones_like(p_big, dtype=torch.bool)
+        mask[tuple(slice(q + 1, q + 1 + n) for n, q in zip(shape, pad))] = False
+        assert torch.equal(p_big[mask], p_before[mask]), "elements outside the solution view changed"
+        if prec != "f32":
+            assert plan.info()["rel_resid"] < 1e-10
+        plan.close()
+
+
+def test_view_in_place_and_contiguous_agree():
+    """rhs and phi the same view (F64): equals a contiguous solve bit for bit."""
+    import paper_1409_8116_amd as mp
+    shape, bc, grid = (24, 30, 18), ("P", "N", "D"), ("v", "s", "s")
+    h = (0.05, 0.04, 0.06)
+    big, view = _padded(shape, (1, 1, 1), torch.float64, 3)
+    contig = view.contiguous()
+    plan = mp.Plan(shape, h, bc, grid, prec="f64")
+    ref = plan.solve(contig)
+    plan.solve_view(view, view)
+    torch.cuda.synchronize()
+    assert torch.allclose(view, ref, rtol=1e-14, atol=1e-14 * float(ref.abs().max()))
+
+
+def test_bad_views_are_refused():
+    import paper_1409_8116_amd as mp
+    plan = mp.Plan((8, 8), (0.1, 0.1), ("D", "D"), ("v", "v"), prec="f64")
+    big = torch.zeros((8, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(mp.MpoisError):
+        plan.solve_view(big[:, ::2].t().contiguous().t(), big[:, 1::2])  # column-major rhs
+    a = torch.zeros((8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(mp.MpoisError):
+        plan.solve_view(a, a[:, :].as_strided((8, 8), (1, 8)))  # overlapping, different layout
+    plan.close()
