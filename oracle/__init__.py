@@ -18,6 +18,8 @@ What it computes follows the paper directly:
 * ``fd``         -- the finite-difference operator of Eq. (FD2) with the
   boundary closures, its dense assembly and a dense LU solve, used to pin
   Table 4 and as the refinement residual reference.
+* ``projection`` -- the projection step of Section 5.1 (divergence of a
+  staggered velocity, the Poisson solve, velocity and pressure correction).
 
 Beyond the paper's tables: axes with a Dirichlet condition on one face and a
 Neumann condition on the other, and a Helmholtz shift (L - sigma) phi = g.
@@ -32,6 +34,8 @@ from .eigen import domain_length, eigenvalues, grid_points
 from .solve import solve, solve_spectrum_scale, zero_mode_is_singular, Axis, axes_from
 from .fd import (apply_laplacian, assemble_1d, assemble, lu_solve, weights,
                  weighted_mean, residual_eta, is_singular)
+from .projection import (divergence, gradient, projection_step, velocity_shapes,
+                         face_count)
 
 __all__ = [
     "transform_matrix", "forward_backward", "dft_matrix", "idft_matrix", "KINDS",
@@ -39,4 +43,5 @@ __all__ = [
     "solve", "solve_spectrum_scale", "zero_mode_is_singular", "Axis", "axes_from",
     "apply_laplacian", "assemble_1d", "assemble", "lu_solve", "weights",
     "weighted_mean", "residual_eta", "is_singular",
+    "divergence", "gradient", "projection_step", "velocity_shapes", "face_count",
 ]

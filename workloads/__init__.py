@@ -194,3 +194,30 @@ def channel_divergence(d, s, seed=5, device="cpu", noise=0.1):
     g = ((torch.roll(u, -1, 0) - u) / dx + (v[:, 1:, :] - v[:, :-1, :]) / dy
          + (torch.roll(w, -1, 2) - w) / dz)
     return g.contiguous()
+
+
+# --------------------------------------------------------------------------- projection step
+def mac_velocity(d, seed=6, std=1.0):
+    """Predicted velocity of a projection step on the staggered (MAC) grid of
+    problem d (every axis periodic or staggered), as float64 numpy arrays.
+
+    Component k has n_k faces along axis k when that axis is periodic and
+    n_k + 1 otherwise (face f on the low side of cell f), and n_j along the
+    other axes.  Entries ~ N(0, std^2); on an axis with a Neumann face the
+    velocity on that boundary face is 0 (no flow through a wall), so the
+    Poisson problem of the projection is solvable.
+    """
+    rng = np.random.default_rng([seed, len(d["shape"])] + list(d["shape"]))
+    vel = []
+    for k, (n, b) in enumerate(zip(d["shape"], d["bc"])):
+        faces = n if b == "P" else n + 1
+        shape = tuple(faces if j == k else m for j, m in enumerate(d["shape"]))
+        u = std * rng.standard_normal(shape)
+        lo, hi = (b, b) if isinstance(b, str) else b
+        um = np.moveaxis(u, k, 0)
+        if b != "P" and lo == "N":
+            um[0] = 0.0
+        if b != "P" and hi == "N":
+            um[n] = 0.0
+        vel.append(u)
+    return vel
