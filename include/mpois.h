@@ -140,6 +140,35 @@ mpois_status mpois_execute(mpois_plan plan, const void* rhs, void* phi, void* st
 mpois_status mpois_execute_view(mpois_plan plan, const void* rhs, const int64_t* rhs_strides, void* phi,
                                 const int64_t* phi_strides, void* stream);
 
+/* Projection step of an incompressible-flow solver (Section 5.1: the
+ * pressure-correction step of each Runge-Kutta stage) on this plan's grid:
+ *   Lap phi = div(u*) / adt,   u = u* - adt grad phi,   p = p + phi,
+ * with second-order differences on the staggered (MAC) grid; adt is
+ * alpha_k * dt of the stage (finite, > 0).
+ * vel: host array of ndim device pointers; vel[d] is the velocity component
+ *   normal to axis d, C order, the plan's shape except along axis d: n_d
+ *   faces when that axis is periodic (face f on the low side of cell f, face
+ *   n_d is face 0), n_d + 1 otherwise (faces 0 and n_d on the boundary).
+ *   It holds u* on entry and the corrected velocity on return.  A Neumann
+ *   boundary face keeps its value (no flux); on a Dirichlet face (phi = 0 on
+ *   it) the gradient is +-2 phi / h from the adjacent cell.
+ * p: pressure at the cells (plan shape, C order), updated in place.
+ * phi: receives phi (plan shape, C order).
+ * Every array has the plan's I/O type (float for MPOIS_F32, else double);
+ * they are distinct device arrays that do not overlap (else INVALID).
+ * Needs an MPOIS_FD2 plan without Helmholtz shift whose axes are all
+ * periodic or staggered (else UNSUPPORTED).  When every axis is periodic or
+ * Neumann, the mean of div(u*) is dropped (phi has zero mean) and the
+ * corrected field keeps that mean as its divergence.
+ * MPOIS_F64 / MPOIS_F32 plans form the divergence inside the first line pass
+ * and correct p and the last axis's component inside the last; the other
+ * components take one more kernel.  MPOIS_F32_REFINE plans form the
+ * divergence into an FP64 array the plan allocates on its first call (NOMEM
+ * if that fails), solve it with refinement and correct afterwards;
+ * mpois_get_info then reports on that solve.  After an FP64 / FP32
+ * projection mpois_get_info returns INVALID (no right-hand side array). */
+mpois_status mpois_project(mpois_plan plan, void* const* vel, void* p, double adt, void* phi, void* stream);
+
 /* Largest scratch the allocation-free execute uses (bytes per device). */
 #define MPOIS_NOALLOC_SCRATCH_BYTES (65u << 20)
 

@@ -75,6 +75,7 @@ def load_library():
     lib.mpois_execute_batch.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
     lib.mpois_execute_noalloc.argtypes = [P, P, P, P]
     lib.mpois_execute_view.argtypes = [P, P, ctypes.POINTER(ctypes.c_int64), P, ctypes.POINTER(ctypes.c_int64), P]
+    lib.mpois_project.argtypes = [P, ctypes.POINTER(P), P, ctypes.c_double, P, P]
     lib.mpois_get_info.argtypes = [P, P, ctypes.POINTER(Info)]
     lib.mpois_destroy.argtypes = [P]
     lib.mpois_workspace_bytes.argtypes = [P]
@@ -90,7 +91,7 @@ def load_library():
         [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.mpois_kernel_shape.argtypes = [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 4
     for name in ("mpois_kernel_shape", "mpois_plan_create", "mpois_plan_create_batch", "mpois_execute", "mpois_execute_batch",
-                 "mpois_execute_noalloc", "mpois_execute_view",
+                 "mpois_execute_noalloc", "mpois_execute_view", "mpois_project",
                  "mpois_get_info", "mpois_destroy", "mpois_validate", "mpois_axis_eigenvalues", "mpois_axis_plan",
                  "mpois_profile"):
         getattr(lib, name).restype = ctypes.c_int
@@ -189,6 +190,7 @@ class Plan:
         self.lib = load_library()
         self.shape = tuple(int(n) for n in shape)
         self.prec = prec
+        self.bc = tuple(bc)
         flags = (FLAG_GRAPH if graph else 0) | (FLAG_TUNE if tune else 0) | (FLAG_PROFILE if profile else 0) | \
             (FLAG_F64_ARITH if f64_arith else 0)
         self._desc = make_desc(shape, h, bc, grid, shift)
@@ -237,6 +239,35 @@ class Plan:
                                          ps, _stream_ptr(stream))
         if st:
             raise MpoisError(st, "mpois_execute_view")
+        return phi
+
+    def velocity_shapes(self):
+        """Shapes of the staggered velocity components a projection step takes:
+        n_d faces along axis d when it is periodic, n_d + 1 otherwise."""
+        out = []
+        for d, b in enumerate(self.bc):
+            per = b == "P" or tuple(b) == ("P", "P")
+            out.append(tuple(n + (0 if (e != d or per) else 1) for e, n in enumerate(self.shape)))
+        return out
+
+    def project(self, vel, p, adt, phi=None, stream=None):
+        """mpois_project: one projection step.  vel (list of ndim tensors, the
+        predicted velocity, corrected in place) and p (pressure, p += phi) as
+        laid out by velocity_shapes(); returns phi."""
+        import torch
+        if len(vel) != len(self.shape):
+            raise ValueError("one velocity component per axis")
+        for u, shp in zip(vel, self.velocity_shapes()):
+            _check_tensor(u, shp, self.dtype, "velocity component")
+        _check_tensor(p, self.shape, self.dtype, "p")
+        if phi is None:
+            phi = torch.empty_like(p)
+        _check_tensor(phi, self.shape, self.dtype, "phi")
+        ptrs = (ctypes.c_void_p * len(vel))(*[u.data_ptr() for u in vel])
+        st = self.lib.mpois_project(self._h, ptrs, ctypes.c_void_p(p.data_ptr()), float(adt),
+                                    ctypes.c_void_p(phi.data_ptr()), _stream_ptr(stream))
+        if st:
+            raise MpoisError(st, "mpois_project")
         return phi
 
     def solve_noalloc(self, rhs, phi, stream=None):

@@ -47,6 +47,25 @@ struct AxisDev {
   const void* cs;     // odd-radix constants
 };
 
+// Projection step of an incompressible-flow solver on the staggered (MAC)
+// grid, axes padded to three (a unit axis has no velocity component).  Face f
+// of axis d lies on the low side of cell f; component d has n[d] + ext[d]
+// faces along axis d (ext 0: periodic, face n is face 0; ext 1: faces 0 and
+// n on the boundary) and n[e] along the other axes, in C order.  The
+// gradient at a boundary face is 0 on a Neumann face (the velocity there is
+// kept) and +-2 phi / h on a Dirichlet face (phi = 0 on the face).
+struct ProjDev {
+  void* vel[3];         // velocity components, corrected in place (null on unit axes)
+  void* p;              // pressure at the cells, p += phi
+  int64_t n[3];
+  int64_t vs[3][3];     // element strides of component d along each axis
+  int ext[3];
+  int dlo[3], dhi[3];   // 1: that boundary face is Dirichlet
+  double inv_h[3];
+  double adt;           // alpha dt: u -= adt grad phi
+  double inv_adt;       // the Poisson right-hand side is div u / adt
+};
+
 // One launch of the line-transform kernel along one axis.
 struct PassArgs {
   const void* src;
@@ -73,6 +92,13 @@ struct PassArgs {
   int64_t src_vnb, src_va, src_vb, src_vd;
   int64_t dst_vnb, dst_va, dst_vb, dst_vd;
   int contig;
+  // Projection step (passes along the last padded axis, C-contiguous phi):
+  // proj_load, the source is div(vel) / adt formed from proj.vel as it is
+  // read; proj_store, the pass also adds phi to proj.p and corrects the
+  // velocity component along the pass axis.
+  int proj_load;
+  int proj_store;
+  ProjDev proj;
 };
 
 // One launch of the line-transform kernel over many grids.

@@ -1170,6 +1170,98 @@ constexpr bool spec_stage_lam() {
   return base + N * int(sizeof(T)) <= half || base > half;
 }
 
+// ----------------------------------------------------------------------------- projection step I/O
+// Quotient and remainder of a non-negative 64-bit index, in 32-bit arithmetic
+// when both operands allow it.
+__device__ __forceinline__ void idx_divmod(int64_t x, int64_t d, int64_t* q, int64_t* r) {
+  if (((x | d) >> 31) == 0) {
+    const uint32_t qq = uint32_t(x) / uint32_t(d);
+    *q = qq;
+    *r = uint32_t(x) - qq * uint32_t(d);
+  } else {
+    *q = x / d;
+    *r = x - *q * d;
+  }
+}
+
+// First pass of a projection step (along the last padded axis): element j of
+// line l is div(vel) / adt at cell (l / n1, l % n1, j), summed in FP64 over
+// the velocity components present.  Lanes take consecutive j of one line, so
+// the three component reads are coalesced.
+template <typename T, typename S, int TL, int NT, int XP>
+__device__ void proj_div_load(T* X, const PassArgs& a, int64_t l0, int n) {
+  const ProjDev& q = a.proj;
+  const int total = TL * n;
+  for (int e = int(threadIdx.x); e < total; e += NT) {
+    const int t = e / n, j = e - t * n;
+    const int64_t l = l0 + t;
+    double sum = 0.0;
+    if (l < a.nlines) {
+      int64_t c[3];
+      idx_divmod(l, q.n[1], &c[0], &c[1]);
+      c[2] = j;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const S* u = static_cast<const S*>(q.vel[d]);
+        if (!u) continue;
+        const int64_t o = c[0] * q.vs[d][0] + c[1] * q.vs[d][1] + c[2] * q.vs[d][2];
+        // the face above cell c; on a periodic axis face n is face 0
+        const int64_t up = (q.ext[d] == 0 && c[d] + 1 == q.n[d]) ? o - (q.n[d] - 1) * q.vs[d][d] : o + q.vs[d][d];
+        sum += (double(u[up]) - double(u[o])) * q.inv_h[d];
+      }
+      sum *= q.inv_adt;
+    }
+    X[j * XP + t] = T(sum);
+  }
+}
+
+// Last pass of a projection step: phi (C order) is stored, added to the
+// pressure, and the velocity component along the pass axis is corrected on
+// its faces from the phi values of the same line (u -= adt grad phi; a
+// Neumann boundary face keeps its value).
+template <typename T, typename D, int TL, int NT, int XP>
+__device__ void proj_store(const T* X, const PassArgs& a, int64_t l0, int n) {
+  const ProjDev& q = a.proj;
+  D* phi = static_cast<D*>(a.dst);
+  D* p = static_cast<D*>(q.p);
+  D* w = static_cast<D*>(q.vel[2]);
+  const int nf = n + q.ext[2];
+  const double cw = q.adt * q.inv_h[2];
+  const int total = TL * nf;
+  for (int e = int(threadIdx.x); e < total; e += NT) {
+    const int t = e / nf, f = e - t * nf;
+    const int64_t l = l0 + t;
+    if (l >= a.nlines) continue;
+    if (f < n) {
+      const double x = double(X[f * XP + t]);
+      const int64_t o = l * int64_t(n) + f;
+      phi[o] = D(x);
+      p[o] = D(double(p[o]) + x);
+    }
+    if (w) {
+      double g;
+      bool upd = true;
+      if (q.ext[2] == 0) {
+        g = double(X[f * XP + t]) - double(X[(f == 0 ? n - 1 : f - 1) * XP + t]);
+      } else if (f == 0) {
+        upd = q.dlo[2] != 0;
+        g = 2.0 * double(X[t]);
+      } else if (f == n) {
+        upd = q.dhi[2] != 0;
+        g = -2.0 * double(X[(n - 1) * XP + t]);
+      } else {
+        g = double(X[f * XP + t]) - double(X[(f - 1) * XP + t]);
+      }
+      if (upd) {
+        int64_t c0, c1;
+        idx_divmod(l, q.n[1], &c0, &c1);
+        const int64_t ow = c0 * q.vs[2][0] + c1 * q.vs[2][1] + f;
+        w[ow] = D(double(w[ow]) - cw * g);
+      }
+    }
+  }
+}
+
 // One sweep over tile `tile`.  AX, KF, KB, ST: length view, forward and
 // inverse kinds (-1: no inverse) and stage list of a kernel specialised for
 // one transform (Ax<>, -2, -2, StageList<>: everything from the description).
@@ -1278,7 +1370,10 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
     const T* lt = static_cast<const T*>(a.lam_this);
     for (int i = int(threadIdx.x); i < AX::Nc; i += NT) lts[i] = lt[i];
   }
-  if (mode == 1) {
+  if (a.proj_load) {
+    if (a.src_f64) proj_div_load<T, double, TL, NT, XP>(X, a, l0, n);
+    else proj_div_load<T, float, TL, NT, XP>(X, a, l0, n);
+  } else if (mode == 1) {
     if (a.src_f64) fast_load(double(0), off_c, xi_c);
     else fast_load(float(0), off_c, xi_c);
   } else if (mode == 2) {
@@ -1329,6 +1424,11 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
       for (int e = 0; e < EF; ++e) *reinterpret_cast<float*>(db + off(tid, e) * 4u) = float(X[xi(tid, e)]);
     }
   };
+  if (a.proj_store) {
+    if (a.dst_f64) proj_store<T, double, TL, NT, XP>(X, a, l0, n);
+    else proj_store<T, float, TL, NT, XP>(X, a, l0, n);
+    return;
+  }
   if (mode == 1) {
     fast_store(off_c, xi_c);
     return;
@@ -1404,6 +1504,7 @@ line_pass_batch(BatchPassArgs b) {
   a.dst_f64 = b.dst_f64;
   a.update = b.update;
   a.shift = (b.update && b.shift_base && a.singular) ? b.shift_base + int64_t(pi) * b.shift_stride : nullptr;
+  a.proj_load = a.proj_store = 0;
   line_pass_body<T, NP, NT, PMAX, RADER, SLIM>(a, int64_t(b.tile_idx[blockIdx.x]), smem);
 }
 

@@ -40,6 +40,8 @@ hipError_t launch_finalize(const double* partials, int nblocks, double inv_wsum,
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 hipError_t launch_line_pass_batch(int cfg, const BatchPassArgs& b, int blocks, size_t lds, hipStream_t s);
 hipError_t launch_resid_batch(const BatchResidArgs& b, int blocks, hipStream_t s);
+hipError_t launch_proj_div(const ProjDev& q, double* g, hipStream_t s);
+hipError_t launch_proj_correct(const ProjDev& q, const void* phi, int f64, int mask, int add_p, hipStream_t s);
 hipError_t launch_finalize_batch(const double* partials, const int* blk_start, const int* blk_count,
                                  const double* inv_wsum, double* scalars, int count, hipStream_t s);
 }  // namespace mpois
@@ -405,6 +407,7 @@ struct mpois_plan_s {
   DevBuf work;       // FP32 working array (refinement)
   DevBuf partials;   // resid partials
   DevBuf scalars;    // S_COUNT doubles per grid
+  DevBuf proj_g;     // FP64 divergence of a projection step (refinement plans, first call)
   size_t bytes = 0;
   const void* last_rhs = nullptr;
   void* last_phi = nullptr;
@@ -937,6 +940,7 @@ void free_plan(mpois_plan_s* pl) {
   dev_free(&pl->work);
   dev_free(&pl->partials);
   dev_free(&pl->scalars);
+  dev_free(&pl->proj_g);
   for (auto& r : pl->prof) (void)hipEventDestroy(r.end);
   if (pl->prof_start) (void)hipEventDestroy(pl->prof_start);
   if (pl->graph.exec) (void)hipGraphExecDestroy(pl->graph.exec);
@@ -1030,7 +1034,7 @@ void set_view(int ax, const int64_t n[3], const int64_t st[3], int64_t* vnb, int
 hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, void* out, int out_f64, void* work,
                      int work_f64, bool update, const double* shift, hipStream_t s,
                      const int64_t* in_view = nullptr, const int64_t* out_view = nullptr,
-                     const int64_t* work_view = nullptr) {
+                     const int64_t* work_view = nullptr, const ProjDev* proj = nullptr) {
   const size_t np = sp.passes.size();
   for (size_t i = 0; i < np; ++i) {
     Pass& p = sp.passes[i];
@@ -1048,6 +1052,14 @@ hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, 
     a.contig = (sv || dv) ? 0 : 1;
     a.update = (last && update) ? 1 : 0;
     a.shift = shift;
+    if (proj) {
+      // projection step: the first pass forms div(vel) / adt as it loads, the
+      // last one corrects p and the last-axis velocity component as it stores
+      a.proj = *proj;
+      a.proj_load = i == 0 ? 1 : 0;
+      a.proj_store = last ? 1 : 0;
+      if (a.proj_load || a.proj_store) a.contig = 0;
+    }
     // the specialised kernels take the contiguous tile paths when they can, and
     // their generic path otherwise (views included)
     hipError_t e = p.spec >= 0 ? launch_spec(p.spec, a, s) : launch_line_pass(p.cfg, a, s);
@@ -1484,6 +1496,92 @@ mpois_status mpois_execute_view(mpois_plan pl, const void* rhs, const int64_t* r
              ? MPOIS_OK
              : MPOIS_ERR_DEVICE;
 }
+
+// Projection step of an incompressible-flow solver on the plan's staggered
+// grid (paper Section 5.1): Lap phi = div(u*) / adt, u = u* - adt grad phi,
+// p += phi.  FP64 / FP32 plans fuse the divergence into the first line pass
+// and the pressure update and the last-axis velocity correction into the
+// last; the other velocity components take one more kernel.  Refinement
+// plans need the right-hand side as an FP64 array for their residuals: the
+// divergence is formed into a plan buffer (allocated on the first call),
+// solved with refinement, and all of the correction runs afterwards.
+mpois_status mpois_project(mpois_plan pl, void* const* vel, void* p, double adt, void* phi, void* stream) {
+  if (!pl || pl->subs.size() != 1 || pl->batched) return MPOIS_ERR_INVALID;
+  SubPlan& sp = pl->subs[0];
+  if (!vel || !p || !phi || !std::isfinite(adt) || !(adt > 0.0)) return MPOIS_ERR_INVALID;
+  if (pl->approx != MPOIS_FD2 || sp.resid.shift != 0.0) return MPOIS_ERR_UNSUPPORTED;
+  const int D = sp.ndim;
+  const size_t es = pl->prec == MPOIS_F32 ? 4 : 8;
+  ProjDev q{};
+  for (int e = 0; e < 3; ++e) {
+    q.n[e] = sp.n[e];
+    q.inv_h[e] = 1.0 / sp.h[e];
+  }
+  std::vector<std::pair<uintptr_t, uintptr_t>> arrays;  // (address, bytes)
+  int mask = 0;
+  for (int d = 0; d < D; ++d) {
+    const int e = 3 - D + d;
+    const bool per = sp.face[e][0] == MPOIS_PERIODIC;
+    if (!per && sp.grid[e] != MPOIS_STAGGERED) return MPOIS_ERR_UNSUPPORTED;
+    if (!vel[d]) return MPOIS_ERR_INVALID;
+    q.vel[e] = vel[d];
+    q.ext[e] = per ? 0 : 1;
+    q.dlo[e] = sp.face[e][0] == MPOIS_DIRICHLET ? 1 : 0;
+    q.dhi[e] = sp.face[e][1] == MPOIS_DIRICHLET ? 1 : 0;
+    int64_t shp[3] = {sp.n[0], sp.n[1], sp.n[2]};
+    shp[e] += q.ext[e];
+    q.vs[e][2] = 1;
+    q.vs[e][1] = shp[2];
+    q.vs[e][0] = shp[1] * shp[2];
+    arrays.push_back({reinterpret_cast<uintptr_t>(vel[d]), uintptr_t(shp[0] * shp[1] * shp[2]) * es});
+    mask |= 1 << e;
+  }
+  q.p = p;
+  q.adt = adt;
+  q.inv_adt = 1.0 / adt;
+  arrays.push_back({reinterpret_cast<uintptr_t>(p), uintptr_t(sp.npts) * es});
+  arrays.push_back({reinterpret_cast<uintptr_t>(phi), uintptr_t(sp.npts) * es});
+  for (size_t i = 0; i < arrays.size(); ++i) {
+    for (size_t j = i + 1; j < arrays.size(); ++j)
+      if (arrays[i].first < arrays[j].first + arrays[j].second && arrays[j].first < arrays[i].first + arrays[i].second)
+        return MPOIS_ERR_INVALID;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, reinterpret_cast<void*>(arrays[i].first)) != hipSuccess) {
+      (void)hipGetLastError();
+      return MPOIS_ERR_INVALID;
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) return MPOIS_ERR_INVALID;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  pl->last_view = false;
+  pl->last_rhs_b.clear();
+  pl->last_phi_b.clear();
+  if (pl->prec == MPOIS_F32_REFINE) {
+    if (!pl->proj_g.p) {
+      const mpois_status st = dev_alloc(pl, &pl->proj_g, size_t(sp.npts) * sizeof(double));
+      if (st != MPOIS_OK) return st;
+    }
+    double* g = static_cast<double*>(pl->proj_g.p);
+    if (launch_proj_div(q, g, s) != hipSuccess) return MPOIS_ERR_DEVICE;
+    if (enqueue_one(pl, sp, 0, g, phi, s, plan_workspace(pl)) != hipSuccess) return MPOIS_ERR_DEVICE;
+    if (launch_proj_correct(q, phi, 1, mask, 1, s) != hipSuccess) return MPOIS_ERR_DEVICE;
+    pl->last_rhs = g;  // mpois_get_info reports on this solve
+    pl->last_phi = phi;
+    pl->last_iters = 1 + pl->max_iter;
+    return MPOIS_OK;
+  }
+  const int f64 = pl->prec == MPOIS_F64 ? 1 : 0;
+  if (run_solve(pl, sp, nullptr, f64, phi, f64, phi, f64, false, nullptr, s, nullptr, nullptr, nullptr, &q) !=
+      hipSuccess)
+    return MPOIS_ERR_DEVICE;
+  mask &= ~4;  // the last pass corrected the last axis's component
+  if (mask && launch_proj_correct(q, phi, f64, mask, 0, s) != hipSuccess) return MPOIS_ERR_DEVICE;
+  pl->last_rhs = nullptr;  // the divergence was never stored
+  pl->last_phi = phi;
+  pl->last_iters = 1;
+  return MPOIS_OK;
+}
+
 
 // ---------------------------------------------------------------------------- allocation-free execute
 // Static scratch of mpois_execute_noalloc: every device the library runs on

@@ -147,3 +147,8 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(m, "_HERE", str(tmp_path))
     with pytest.raises(RuntimeError):
         m.load_library()
+
+
+def test_project_null_arguments(mp):
+    lib = mp.load_library()
+    assert lib.mpois_project(None, None, None, 0.5, None, None) == 1
