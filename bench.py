@@ -17,6 +17,9 @@ The same line carries the other workloads under "configs" (default
               autotuned plans
   channel     1024x512x256 channel, graph-captured FP32 + refinement, a stream
               of right-hand sides
+  projection  one projection step (divergence, solve, velocity and pressure
+              correction) on the staggered 1024x512x256 channel, FP64 fused
+              and FP32 + refinement
   copy        plain 1 GiB device-to-device copy (calibrates the HBM byte counters)
 Each entry: ms per step, grid points/s, algorithmic HBM GB/s and the error
 against the oracle on its sample.  Progress goes to stderr.
@@ -317,7 +320,7 @@ def run_channel(args):
     d = workloads.channel_desc()
     npts = int(np.prod(d["shape"]))
     nrhs = args.nrhs
-    plan = mp.Plan.from_desc(d, prec="f32r", max_iter=1, graph=True)
+    plan = mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, graph=True)
     rhs = torch.empty(d["shape"], dtype=torch.float64, device="cuda")
     phi = torch.empty_like(rhs)
     # the graph is captured for this (rhs, phi) pair; each step regenerates rhs in place
@@ -339,8 +342,9 @@ def run_channel(args):
         if s % 50 == 0 or s == nrhs - 1:
             worst_resid = max(worst_resid, plan.info()["rel_resid"])
     ms = total / nrhs
-    recs, reps = profile_plan(lambda: mp.Plan.from_desc(d, prec="f32r", max_iter=1, profile=True), rhs)
+    recs, reps = profile_plan(lambda: mp.Plan.from_desc(d, prec="f32r", max_iter=args.max_iter, profile=True), rhs)
     out = {"workload": f"channel_1024x512x256_P-Ns-P_graph_f32r_{nrhs}rhs", "ms_per_rhs": ms,
+           "refine_corrections": args.max_iter,
            "points_per_s": npts / (ms * 1e-3), "hbm_gbs_step": step_gbs(recs, reps, ms),
            "roofline": kernel_roofline(recs, reps), "rel_resid_worst_sampled": worst_resid}
     log(f"[channel] {ms:.3f} ms per right-hand side, {out['hbm_gbs_step']:.0f} GB/s")
@@ -351,6 +355,75 @@ def run_channel(args):
                                "sample": "one 1024x512x256 solve (rhs #0)"}
         log(f"[channel] rel err rhs #0 {out['rel_err_vs_oracle_rhs0']:.2e}")
     plan.close()
+    return out
+
+
+def run_projection(args):
+    """One projection step of the channel flow (Section 5.1) per step: the
+    divergence of a staggered velocity, the solve and the velocity / pressure
+    correction, FP64 (fused into the first and last line passes) and FP32 +
+    refinement, next to the plain solve of the same grid."""
+    import torch
+    import workloads
+    import paper_1409_8116_amd as mp
+    d = workloads.channel_desc()
+    d = dict(d, grid=("s", "s", "s"))
+    shape = d["shape"]
+    npts = int(np.prod(shape))
+    log("[projection] generating the staggered velocity")
+    vel0 = workloads.mac_velocity(d, seed=9)
+    p0 = np.random.default_rng(10).standard_normal(shape)
+    vel = [torch.tensor(u, device="cuda") for u in vel0]
+    p = torch.tensor(p0, device="cuda")
+    phi = torch.empty_like(p)
+    work = [torch.empty_like(u) for u in vel]
+    pw = torch.empty_like(p)
+    adt = 0.02
+    out = {"workload": "projection_1024x512x256_P-Ns-P_staggered"}
+
+    def step(plan):
+        for w, u in zip(work, vel):
+            w.copy_(u)
+        pw.copy_(p)
+        plan.project(work, pw, adt, phi)
+
+    # the copies that restore u* and p each step are timed on their own and removed
+    copy_ms, _ = timed(lambda: ([w.copy_(u) for w, u in zip(work, vel)], pw.copy_(p)), args.steps, args.warmup)
+    # algorithmic bytes per point of the fused FP64 step: pass 1 reads three
+    # velocity components and writes phi (32), three middle passes (48), the
+    # last pass reads phi, p, w and writes them (48), the u / v correction
+    # reads phi, u, v and writes u, v (40)
+    fused_bytes = 168.0
+    for prec, k in (("f64", 0), ("f32r", args.max_iter)):
+        plan = mp.Plan.from_desc(d, prec=prec, max_iter=max(k, 1))
+        ms, _ = timed(lambda: step(plan), args.steps, args.warmup)
+        ms -= copy_ms
+        solve_ms, _ = timed(lambda: plan.solve(pw, phi), args.steps, args.warmup)
+        rec = {"ms_per_step": ms, "points_per_s": npts / (ms * 1e-3), "plain_solve_ms": solve_ms}
+        if prec == "f64":
+            rec["hbm_gbs_step"] = npts * fused_bytes / (ms * 1e-3) / 1e9
+        else:
+            rec["refine_corrections"] = k
+        step(plan)
+        torch.cuda.synchronize()
+        if prec == "f32r":
+            rec["rel_resid"] = plan.info()["rel_resid"]
+        out[prec] = rec
+        log(f"[projection] {prec}: {ms:.3f} ms per step (plain solve {solve_ms:.3f} ms)")
+        plan.close()
+    if not args.no_cpu:
+        import oracle
+        axes = oracle.axes_from(shape, d["h"], d["bc"], d["grid"])
+        t0 = time.perf_counter()
+        rv, rp, rphi = oracle.projection_step(vel0, p0, axes, adt)
+        dt = time.perf_counter() - t0
+        out["rel_err_vs_oracle_f32r"] = {
+            "phi": rel(phi, rphi),
+            "velocity": max(float(np.linalg.norm(w.cpu().numpy() - r) / np.linalg.norm(u))
+                            for w, r, u in zip(work, rv, vel0))}
+        out["cpu_baseline"] = {"value": npts / dt, "unit": "points/s", "cores": cpu_threads(), "kind": "oracle",
+                               "sample": "one projection step of the same field"}
+        log(f"[projection] oracle {dt:.1f} s, rel err phi {out['rel_err_vs_oracle_f32r']['phi']:.2e}")
     return out
 
 
@@ -366,7 +439,7 @@ def run_copy(args):
 
 
 SECONDARY = {"periodic32": run_periodic32, "mixed256": run_mixed256, "batch2048": run_batch,
-             "channel": run_channel}
+             "channel": run_channel, "projection": run_projection}
 
 
 def main():

@@ -75,12 +75,23 @@ def build(verbose=False, jobs=None, incremental=False):
     for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        while sum(p.poll() is None for p in running) >= jobs:
+        while sum(p.poll() is None for p, _ in running) >= jobs:
             time.sleep(0.2)
-        running.append(subprocess.Popen(cmd))
-    for p in running:
-        if p.wait() != 0:
-            raise RuntimeError("hipcc failed")
+        # the compiler's resource-usage remarks of every kernel go to a log next
+        # to the object, checked below
+        log = open(cmd[-1] + ".usage", "w")
+        running.append((subprocess.Popen(cmd + ["-Rpass-analysis=kernel-resource-usage"], stderr=log), log))
+    for p, log in running:
+        rc = p.wait()
+        log.close()
+        if rc != 0:
+            raise RuntimeError("hipcc failed: " + open(log.name).read()[-4000:])
+    small, large = scratch_kernels(objs)
+    if small and verbose:
+        print("kernels with a few spilled registers: " + ", ".join(small), flush=True)
+    if large:
+        raise RuntimeError("kernels that keep data in scratch memory (a demoted array or struct, or heavy "
+                           "register spills): " + ", ".join(large))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
@@ -88,6 +99,30 @@ def build(verbose=False, jobs=None, incremental=False):
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
+
+
+def scratch_kernels(objs, limit=64):
+    """Kernels whose resource-usage remark reports scratch (private) memory:
+    (those with at most `limit` bytes per lane, those with more).  The
+    kernels keep their data in registers and LDS; a few spilled registers
+    (the FP64 shapes held to 128 registers) cost little, but an array or
+    struct demoted to scratch costs several times the kernel's time, so the
+    build refuses that."""
+    import re
+    bad = []
+    for obj in objs:
+        path = obj + ".usage"
+        if not os.path.exists(path):
+            continue
+        name = None
+        for line in open(path):
+            m = re.search(r"Function Name: (\S+)", line)
+            if m:
+                name = m.group(1)
+            m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+            if m and int(m.group(1)) > 0 and name:
+                bad.append((f"{name} ({m.group(1)} B/lane)", int(m.group(1))))
+    return [b for b, v in bad if v <= limit], [b for b, v in bad if v > limit]
 
 
 if __name__ == "__main__":

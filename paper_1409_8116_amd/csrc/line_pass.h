@@ -1189,7 +1189,7 @@ __device__ __forceinline__ void idx_divmod(int64_t x, int64_t d, int64_t* q, int
 // the velocity components present.  Lanes take consecutive j of one line, so
 // the three component reads are coalesced.
 template <typename T, typename S, int TL, int NT, int XP>
-__device__ void proj_div_load(T* X, const PassArgs& a, int64_t l0, int n) {
+__device__ __forceinline__ void proj_div_load(T* X, const PassArgs& a, int64_t l0, int n) {
   const ProjDev& q = a.proj;
   const int total = TL * n;
   for (int e = int(threadIdx.x); e < total; e += NT) {
@@ -1220,7 +1220,7 @@ __device__ void proj_div_load(T* X, const PassArgs& a, int64_t l0, int n) {
 // its faces from the phi values of the same line (u -= adt grad phi; a
 // Neumann boundary face keeps its value).
 template <typename T, typename D, int TL, int NT, int XP>
-__device__ void proj_store(const T* X, const PassArgs& a, int64_t l0, int n) {
+__device__ __forceinline__ void proj_store(const T* X, const PassArgs& a, int64_t l0, int n) {
   const ProjDev& q = a.proj;
   D* phi = static_cast<D*>(a.dst);
   D* p = static_cast<D*>(q.p);
@@ -1266,8 +1266,10 @@ __device__ void proj_store(const T* X, const PassArgs& a, int64_t l0, int n) {
 // inverse kinds (-1: no inverse) and stage list of a kernel specialised for
 // one transform (Ax<>, -2, -2, StageList<>: everything from the description).
 // ZP: LDS row pitch in complex values (NP for the generic shapes).
+// PROJ: the kernel also serves the first and last passes of a projection step
+// (a separate instantiation, so that the other kernels carry none of its code).
 template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM, class AX = Ax<>, int KF = -2, int KB = -2,
-          class ST = StageList<>, int ZP = NP>
+          class ST = StageList<>, int ZP = NP, bool PROJ = false>
 __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, unsigned char* smem) {
   static_assert(ZP == NP || (KF >= 0 && ST::count > 0 && AX::ct), "a padded pitch needs a specialised kernel");
   constexpr int TL = 2 * NP;
@@ -1370,9 +1372,11 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
     const T* lt = static_cast<const T*>(a.lam_this);
     for (int i = int(threadIdx.x); i < AX::Nc; i += NT) lts[i] = lt[i];
   }
-  if (a.proj_load) {
-    if (a.src_f64) proj_div_load<T, double, TL, NT, XP>(X, a, l0, n);
-    else proj_div_load<T, float, TL, NT, XP>(X, a, l0, n);
+  if (PROJ && a.proj_load) {
+    if constexpr (PROJ) {
+      if (a.src_f64) proj_div_load<T, double, TL, NT, XP>(X, a, l0, n);
+      else proj_div_load<T, float, TL, NT, XP>(X, a, l0, n);
+    }
   } else if (mode == 1) {
     if (a.src_f64) fast_load(double(0), off_c, xi_c);
     else fast_load(float(0), off_c, xi_c);
@@ -1424,10 +1428,12 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
       for (int e = 0; e < EF; ++e) *reinterpret_cast<float*>(db + off(tid, e) * 4u) = float(X[xi(tid, e)]);
     }
   };
-  if (a.proj_store) {
-    if (a.dst_f64) proj_store<T, double, TL, NT, XP>(X, a, l0, n);
-    else proj_store<T, float, TL, NT, XP>(X, a, l0, n);
-    return;
+  if constexpr (PROJ) {
+    if (a.proj_store) {
+      if (a.dst_f64) proj_store<T, double, TL, NT, XP>(X, a, l0, n);
+      else proj_store<T, float, TL, NT, XP>(X, a, l0, n);
+      return;
+    }
   }
   if (mode == 1) {
     fast_store(off_c, xi_c);
@@ -1489,6 +1495,15 @@ line_pass(PassArgs a) {
   line_pass_body<T, NP, NT, PMAX, RADER, SLIM>(a, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
+// The same with the projection-step loads and stores.
+template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM, RADER>::v, 8)))
+line_pass_proj(PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  line_pass_body<T, NP, NT, PMAX, RADER, SLIM, Ax<>, -2, -2, StageList<>, NP, true>(a, xcd_tile(blockIdx.x, gridDim.x),
+                                                                                  smem);
+}
+
 // Many grids in one launch: block b works on tile tile_idx[b] of grid
 // tile_prob[b]; the per-grid pass description comes from a device table and
 // the array pointers from per-grid pointer tables.
@@ -1504,7 +1519,6 @@ line_pass_batch(BatchPassArgs b) {
   a.dst_f64 = b.dst_f64;
   a.update = b.update;
   a.shift = (b.update && b.shift_base && a.singular) ? b.shift_base + int64_t(pi) * b.shift_stride : nullptr;
-  a.proj_load = a.proj_store = 0;
   line_pass_body<T, NP, NT, PMAX, RADER, SLIM>(a, int64_t(b.tile_idx[blockIdx.x]), smem);
 }
 
@@ -1512,7 +1526,10 @@ template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
 hipError_t launch_lp(const PassArgs& a, hipStream_t s, size_t lds) {
   constexpr int64_t TL = 2 * NP;
   const int64_t blocks = (a.nlines + TL - 1) / TL;
-  hipLaunchKernelGGL((line_pass<T, NP, NT, PMAX, RADER, SLIM>), dim3(unsigned(blocks)), dim3(NT), lds, s, a);
+  if (a.proj_load || a.proj_store)
+    hipLaunchKernelGGL((line_pass_proj<T, NP, NT, PMAX, RADER, SLIM>), dim3(unsigned(blocks)), dim3(NT), lds, s, a);
+  else
+    hipLaunchKernelGGL((line_pass<T, NP, NT, PMAX, RADER, SLIM>), dim3(unsigned(blocks)), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1560,6 +1577,9 @@ template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
 hipError_t prepare_lp() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass<T, NP, NT, PMAX, RADER, SLIM>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass_proj<T, NP, NT, PMAX, RADER, SLIM>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&line_pass_batch<T, NP, NT, PMAX, RADER, SLIM>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

@@ -349,6 +349,7 @@ struct SubPlan {
   std::vector<DevBuf> lam;      // scaled eigenvalues per axis (working precision)
   std::vector<Pass> passes;     // forward ... fused ... inverse
   ResidArgs resid{};
+  int rperm[3] = {0, 1, 2};     // residual axis e is padded axis rperm[e]
 };
 
 // Per-launch record of a profiled execute.
@@ -910,6 +911,18 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
     r.inv_h2[e] = real_axis ? 1.0 / (sp->h[e] * sp->h[e]) : 0.0;
   }
   r.shift = g->shift;
+  if (D == 2) {
+    // the residual kernel marches along its axis 0 with the neighbours in
+    // registers: give it the grid's first axis rather than the unit one
+    std::swap(r.n[0], r.n[1]);
+    std::swap(r.ps[0], r.ps[1]);
+    std::swap(r.gs[0], r.gs[1]);
+    std::swap(r.clo[0], r.clo[1]);
+    std::swap(r.chi[0], r.chi[1]);
+    std::swap(r.inv_h2[0], r.inv_h2[1]);
+    sp->rperm[0] = 1;
+    sp->rperm[1] = 0;
+  }
   return MPOIS_OK;
 }
 
@@ -1062,10 +1075,12 @@ hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, 
     }
     // the specialised kernels take the contiguous tile paths when they can, and
     // their generic path otherwise (views included)
-    hipError_t e = p.spec >= 0 ? launch_spec(p.spec, a, s) : launch_line_pass(p.cfg, a, s);
+    // (the projection loads and stores exist in the generic kernels only)
+    const bool spec = p.spec >= 0 && !(a.proj_load || a.proj_store);
+    hipError_t e = spec ? launch_spec(p.spec, a, s) : launch_line_pass(p.cfg, a, s);
     if (e != hipSuccess) return e;
     const double pts = double(sp.npts);
-    prof_mark(pl, p.spec >= 0 ? kSpecBase + p.spec : p.cfg, pts * ((a.src_f64 ? 8 : 4) + (a.dst_f64 ? 8 : 4) + (a.update ? 8 : 0)), s);
+    prof_mark(pl, spec ? kSpecBase + p.spec : p.cfg, pts * ((a.src_f64 ? 8 : 4) + (a.dst_f64 ? 8 : 4) + (a.update ? 8 : 0)), s);
   }
   return hipSuccess;
 }
@@ -1088,8 +1103,8 @@ hipError_t run_resid(mpois_plan_s* pl, SubPlan& sp, const void* rhs, const void*
                      const IoViews& views = IoViews()) {
   ResidArgs a = sp.resid;
   for (int e = 0; e < 3; ++e) {
-    if (views.phi) a.ps[e] = views.phi[e];
-    if (views.rhs) a.gs[e] = views.rhs[e];
+    if (views.phi) a.ps[e] = views.phi[sp.rperm[e]];
+    if (views.rhs) a.gs[e] = views.rhs[sp.rperm[e]];
   }
   a.phi = static_cast<const double*>(phi);
   a.g = static_cast<const double*>(rhs);
@@ -1179,7 +1194,8 @@ mpois_status build_batch(mpois_plan_s* pl) {
     rargs[i] = sp.resid;
     rargs[i].singular = sp.singular ? 1 : 0;
     B.any_singular = B.any_singular || sp.singular;
-    const int64_t units = sp.n[1] * ((sp.n[2] + 255) / 256) * ((sp.n[0] + 31) / 32);  // residual work units
+    const int64_t* rn = sp.resid.n;
+    const int64_t units = rn[1] * ((rn[2] + 255) / 256) * ((rn[0] + 31) / 32);  // residual work units
     int64_t nb = (sp.npts + 8191) / 8192;
     nb = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(nb, 256), units));
     blk_start[i] = int(blk_prob.size());

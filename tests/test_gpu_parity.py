@@ -306,7 +306,7 @@ def test_channel_full_size_first_and_last_rhs():
     turn, each against the oracle."""
     d = workloads.channel_desc()
     mp = _mp()
-    plan = mp.Plan.from_desc(d, prec="f32r", max_iter=1, graph=True)
+    plan = mp.Plan.from_desc(d, prec="f32r", max_iter=2, graph=True)
     rhs = torch.empty(d["shape"], dtype=torch.float64, device="cuda")
     phi = torch.empty_like(rhs)
     for s in (0, 199):
@@ -317,7 +317,7 @@ def test_channel_full_size_first_and_last_rhs():
         ref = oracle_solve(rhs.cpu().numpy(), d["shape"], d["h"], d["bc"], d["grid"], "fd")
         err = rel_err(phi.cpu().numpy(), ref)
         print(f"[parity] channel rhs #{s} rel err {err:.3e} resid {info['rel_resid']:.3e}", flush=True)
-        assert err <= 1e-10, (s, err)
+        assert err <= 1e-12, (s, err)
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
