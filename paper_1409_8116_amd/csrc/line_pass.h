@@ -1487,6 +1487,15 @@ struct MinWaves {
   static constexpr int v = SLIM ? 4 : (RADER ? 2 : 1);
 };
 
+// The batched kernel of a full (non-slim, non-Rader) FP32 shape: held to 128
+// registers as well.  Left free it took a few registers more than the
+// one-grid kernel (the table reads) and fell to 3 waves per SIMD, one
+// 512-thread workgroup per CU.  (The FP64 ones would spill.)
+template <typename T, int SLIM, int RADER>
+struct MinWavesBatch {
+  static constexpr int v = RADER ? 2 : (SLIM || sizeof(T) == 4) ? 4 : 1;
+};
+
 // One grid: block b owns tile b.
 template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM, RADER>::v, 8)))
@@ -1508,7 +1517,7 @@ line_pass_proj(PassArgs a) {
 // tile_prob[b]; the per-grid pass description comes from a device table and
 // the array pointers from per-grid pointer tables.
 template <typename T, int NP, int NT, int PMAX, int RADER, int SLIM>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM, RADER>::v, 8)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWavesBatch<T, SLIM, RADER>::v, 8)))
 line_pass_batch(BatchPassArgs b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int pi = b.tile_prob[blockIdx.x];

@@ -236,6 +236,7 @@ struct AxisShape {
   int64_t M = 0, P = 0;
   bool bluestein = false;
   std::vector<int> radices;
+  int tag = 0;  // which candidate of axis_variants: 0 default, 1 reversed, 2 one more stage, 3 Bluestein
 };
 
 AxisShape plan_axis_shape(int bc, int grid, int64_t n, bool f64) {
@@ -271,10 +272,12 @@ std::vector<AxisShape> axis_variants(int bc, int grid, int64_t n, bool f64) {
   if (d.radices.size() >= 2) {
     AxisShape r = d;
     std::reverse(r.radices.begin(), r.radices.end());
+    r.tag = 1;
     add(r);
   }
   {
     AxisShape x = d;
+    x.tag = 2;
     if (factor_radices(d.P, f64, !d.bluestein, &x.radices, 1)) add(x);
   }
   bool big_odd = false;
@@ -282,6 +285,7 @@ std::vector<AxisShape> axis_variants(int bc, int grid, int64_t n, bool f64) {
   if (!d.bluestein && big_odd && d.M > 1) {
     AxisShape b = d;
     b.bluestein = true;
+    b.tag = 3;
     b.P = 2 * d.M - 1;
     while (!factor_radices(b.P, f64, false, &b.radices)) ++b.P;
     add(b);
@@ -737,40 +741,63 @@ int table_for(mpois_plan_s* pl, int bc, int grid, int64_t n, const AxisShape& sh
 
 // Measured choice of radix plan and kernel shape for one pass (MPOIS_FLAG_TUNE).
 // Candidates: every radix plan of axis_variants times every kernel shape that
-// holds it; each is timed on scratch arrays with the pass's line count (for
-// batch plans a fixed count of at least 2048 lines: their passes share the
-// chip with the other grids', so throughput per line is what counts).  The
-// decision is cached under a key of precision, kinds, axis kind, length,
-// stride class and line count.  Returns the index of the chosen plan's
-// tables (and the shape in *cfg), or -1 if nothing could be measured.
+// holds it, each timed on scratch arrays.  Single-grid plans time the pass's
+// own line count and cache the decision per (precision, kinds, axis kind,
+// length, stride class, line count).  Batch plans share the chip with the
+// other grids, so per-line throughput at full occupancy is what counts: each
+// candidate runs at least 2048 workgroups' worth of lines, and the decision
+// (a variant tag and a shape) is made once per bucket of similar passes --
+// precision, kinds, axis kind, stride class, radix family (Rader, radix
+// 11/13, Bluestein or smooth) and the power-of-two size class of the work
+// length -- from its first member, then reused by the others.  Returns the
+// index of the chosen plan's tables (and the shape in *cfg), or -1 if
+// nothing could be measured.
 int tune_axis_pass(mpois_plan_s* pl, const PassArgs& proto, int bc, int grid, int64_t n, int* cfg,
                    mpois_status* st) {
   const bool f64 = pl->f64work;
+  const bool batch = pl->subs.size() > 1;
   const std::vector<AxisShape> vars = axis_variants(bc, grid, n, f64);
-  int64_t lines = proto.nlines;
-  if (pl->subs.size() > 1) {
-    lines = std::max<int64_t>(lines, 2048);
-    lines = (lines + proto.inner - 1) / proto.inner * proto.inner;
+  const AxisShape& d0 = vars[0];
+  std::string key = std::string(f64 ? "f64" : "f32") + "/kf" + std::to_string(proto.kind_f) + "/kb" +
+                    std::to_string(proto.kind_b) + "/bc" + std::to_string(bc) + std::to_string(grid) +
+                    (proto.inner == 1 ? "/c" : "/s");
+  if (batch) {
+    int pc = 0;
+    while ((int64_t(1) << pc) < d0.P) ++pc;
+    const char* fam = has_rader(d0) ? "r" : has_odd_large(d0) ? "o" : d0.bluestein ? "b" : "s";
+    key += std::string("/tput/") + fam + std::to_string(pc) + "/";
+    // and how many workgroups of each shape fit a CU (LDS) at this length:
+    // members of a bucket then see the same occupancy per shape
+    for (int c = 0; c < num_kernel_cfgs(); ++c) {
+      const bool fits = cfg_fits(c, f64, int(n), int(d0.P), has_rader(d0), has_odd_large(d0));
+      const size_t lds = line_pass_lds(c, int(n), int(d0.P));
+      key += fits ? char('0' + std::min<size_t>(4, size_t(kMaxLds) * 2 / std::max<size_t>(lds, 1) / 2)) : '-';
+    }
+  } else {
+    key += "/n" + std::to_string(n) + "/l" + std::to_string(proto.nlines);
   }
-  const std::string key = std::string(f64 ? "f64" : "f32") + "/kf" + std::to_string(proto.kind_f) + "/kb" +
-                          std::to_string(proto.kind_b) + "/bc" + std::to_string(bc) + std::to_string(grid) + "/n" +
-                          std::to_string(n) + (proto.inner == 1 ? "/c" : "/s") +
-                          (pl->subs.size() > 1 ? std::string("/tput") : "/l" + std::to_string(lines));
   // MPOIS_TUNE_VARIANT=k restricts the candidates to radix plan k of
   // axis_variants (when it exists), bypassing the cache: a test hook that
   // makes every plan variant reachable.
   const char* force = std::getenv("MPOIS_TUNE_VARIANT");
   const int only = force ? std::atoi(force) : -1;
-  int vi = -1, ci = -1;
-  if (only < 0 && tune_lookup(key, &vi, &ci) && vi >= 0 && vi < int(vars.size()) &&
-      cfg_fits(ci, f64, int(n), int(vars[vi].P), has_rader(vars[vi]), has_odd_large(vars[vi]))) {
-    *cfg = ci;
-    return table_for(pl, bc, grid, n, vars[vi], st);
+  int tag = -1, ci = -1;
+  if (only < 0 && tune_lookup(key, &tag, &ci)) {
+    // the variant with the stored tag (else the default) and the stored shape
+    // when it holds this length (else the default shape)
+    size_t v = 0;
+    for (size_t i = 0; i < vars.size(); ++i)
+      if (vars[i].tag == tag) v = i;
+    const AxisShape& sh = vars[v];
+    const bool fits = ci >= 0 && cfg_fits(ci, f64, int(n), int(sh.P), has_rader(sh), has_odd_large(sh));
+    *cfg = fits ? ci : default_cfg(f64, int(n), int(sh.P), has_rader(sh), has_odd_large(sh));
+    if (*cfg < 0) return -1;
+    return table_for(pl, bc, grid, n, sh, st);
   }
   if (!pl->tune) pl->tune = tune_begin();
   double best = 1e300;
-  int best_t = -1;
-  vi = ci = -1;
+  int best_t = -1, best_tag = -1;
+  ci = -1;
   for (size_t v = 0; v < vars.size(); ++v) {
     if (only >= 0 && only < int(vars.size()) && int(v) != only) continue;
     const AxisShape& sh = vars[v];
@@ -780,19 +807,32 @@ int tune_axis_pass(mpois_plan_s* pl, const PassArgs& proto, int bc, int grid, in
     a.ax = pl->tables[t].dev;
     for (int c = 0; c < num_kernel_cfgs(); ++c) {
       if (!cfg_fits(c, f64, int(n), int(sh.P), has_rader(sh), has_odd_large(sh))) continue;
-      const double ms = tune_time(pl->tune, a, c, lines);
+      int cf64, np, nt, pmax;
+      kernel_cfg(c, &cf64, &np, &nt, &pmax);
+      int64_t lines = proto.nlines;
+      if (batch) {
+        lines = std::max<int64_t>(lines, int64_t(2048) * 2 * np);
+        lines = (lines + proto.inner - 1) / proto.inner * proto.inner;
+      }
+      const double ms = batch ? tune_time_batch(pl->tune, a, c, lines) : tune_time(pl->tune, a, c, lines);
+      const double per_line = ms / double(lines);
       if (std::getenv("MPOIS_LOG"))
-        std::fprintf(stderr, "[mpois tune] %s plan %zu shape %d: %.4f ms\n", key.c_str(), v, c, ms);
-      if (ms >= 0 && ms < best) {
-        best = ms;
+        std::fprintf(stderr, "[mpois tune] %s n%lld plan %zu shape %d: %.4f ms over %lld lines\n", key.c_str(),
+                     static_cast<long long>(n), v, c, ms, static_cast<long long>(lines));
+      if (ms >= 0 && per_line < best) {
+        best = per_line;
         best_t = t;
-        vi = int(v);
+        best_tag = sh.tag;
         ci = c;
       }
     }
   }
   if (best_t < 0) return -1;
-  if (only < 0) tune_store(key, vi, ci);
+  if (std::getenv("MPOIS_LOG"))
+    std::fprintf(stderr, "[mpois tune] %s n%lld -> plan tag %d shape %d (untuned shape %d)\n", key.c_str(),
+                 static_cast<long long>(n), best_tag, ci,
+                 default_cfg(f64, int(n), int(d0.P), has_rader(d0), has_odd_large(d0)));
+  if (only < 0) tune_store(key, best_tag, ci);
   *cfg = ci;
   return best_t;
 }

@@ -19,6 +19,10 @@ void tune_end(TuneSession* t);
 // `lines` overrides the pass's line count (throughput measurement for batches).
 double tune_time(TuneSession* t, const PassArgs& proto, int cfg, int64_t lines);
 
+// The same pass as one grid of the batched kernel (the kernel batches run),
+// over `lines` lines (C-contiguous scratch).
+double tune_time_batch(TuneSession* t, const PassArgs& proto, int cfg, int64_t lines);
+
 // Cache of earlier decisions, per process and, when the environment variable
 // MPOIS_TUNE_CACHE names a file, in that file (one "<device> <key> <a> <b>"
 // line per decision; the device string holds the gfx architecture, the
