@@ -210,7 +210,8 @@ size_t mpois_workspace_bytes(mpois_plan plan);
  * events on the execute's stream; bytes[i] its algorithmic HBM bytes (each
  * input element read once, each output written once); kernel[i] the
  * line-transform kernel (generic shapes below 100, kernels specialised for
- * one transform from 200), 100 for the residual, 101 for the reduction.
+ * one transform from 200, plane kernels from 300), 100 for the residual, 101
+ * for the reduction.
  * Writes min(cap, *count) entries; *count receives the number of launches.
  * Synchronises `stream`. */
 mpois_status mpois_profile(mpois_plan plan, void* stream, int cap, double* ms, double* bytes, int* kernel,
@@ -241,8 +242,10 @@ mpois_status mpois_axis_plan(int bc, int grid, int64_t n, int* kind_fwd, int* ki
 /* Shape of line-transform kernel `cfg` (the kernel ids reported by
  * mpois_profile): element size in bytes, line pairs per workgroup tile,
  * threads per workgroup, and the longest DFT work length -- or, for the
- * kernels specialised for one transform (ids 200 and up), its line length.
- * INVALID if out of range. */
+ * kernels specialised for one transform (ids 200 and up), its line length;
+ * for the plane kernels that transform the last two axes of a small 3D grid
+ * in one sweep (ids 300 and up: one workgroup per n x n plane), n / 2 pairs
+ * and n.  INVALID if out of range. */
 mpois_status mpois_kernel_shape(int cfg, int* elem_bytes, int* pairs, int* threads, int* max_len);
 
 #ifdef __cplusplus

@@ -158,6 +158,8 @@ def kernel_shape_name(cfg):
     if st:
         return f"line_pass#{cfg}"
     t = "double" if v[0].value == 8 else "float"
+    if cfg >= 300:
+        return f"plane_pass#{cfg - 300}<{t}, {v[2].value}, n={v[3].value}>"
     if cfg >= 200:
         return f"line_pass_spec#{cfg - 200}<{t}, {v[1].value}, {v[2].value}, n={v[3].value}>"
     return f"line_pass<{t}, {v[1].value}, {v[2].value}, {v[3].value}>"

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpois.so")
-SOURCES = ["aux.hip", "proj.hip", "dispatch.cpp", "mpois.cpp", "tune.cpp"]
+SOURCES = ["aux.hip", "proj.hip", "pl_inst.hip", "dispatch.cpp", "mpois.cpp", "tune.cpp"]
 def _count(header, macro):
     import re
     with open(os.path.join(CSRC, header)) as fh:

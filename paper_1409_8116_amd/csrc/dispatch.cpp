@@ -5,6 +5,7 @@
 
 #include "cfgs.h"
 #include "internal.h"
+#include "planes.h"
 #include "specs.h"
 
 namespace mpois {
@@ -26,7 +27,26 @@ MPOIS_DECL(14) MPOIS_DECL(15)
 MPOIS_SPECS(MPOIS_DECL_SPEC)
 #undef MPOIS_DECL_SPEC
 
+// one per plane kernel, defined in pl_inst.hip
+#define MPOIS_DECL_PLANE(ID, ...) \
+  hipError_t launch_plane_##ID(const PassArgs& a2, const PassArgs& a1, int inverse, int64_t planes, hipStream_t s);
+MPOIS_PLANES(MPOIS_DECL_PLANE)
+#undef MPOIS_DECL_PLANE
+
 namespace {
+struct PlaneInfo {
+  int f64, nt, n, M, P, kf, kb;
+  std::vector<int> radices;
+  hipError_t (*launch)(const PassArgs&, const PassArgs&, int, int64_t, hipStream_t);
+};
+const PlaneInfo kPlanes[] = {
+#define X(ID, T, NT, N, M, P, KF, KB, ...) {sizeof(T) == 8, NT, N, M, P, KF, KB, {__VA_ARGS__}, &launch_plane_##ID},
+    MPOIS_PLANES(X)
+#undef X
+};
+constexpr int kNumPlanes = sizeof(kPlanes) / sizeof(kPlanes[0]);
+static_assert(kNumPlanes == MPOIS_NUM_PLANES, "plane list and count disagree");
+
 struct SpecInfo {
   int f64, np, nt, rader, pad, n, M, P, kf, kb;
   std::vector<int> radices;
@@ -141,6 +161,30 @@ size_t spec_lds(int i) {
 hipError_t launch_spec(int i, const PassArgs& a, hipStream_t s) {
   if (i < 0 || i >= kNumSpecs) return hipErrorInvalidValue;
   return kSpecs[i].launch(a, s, spec_lds(i));
+}
+
+// Plane kernel for two axes whose passes have these parameters, or -1.
+int find_plane(bool f64, int n, int M, int P, int kind_f, int kind_b, const std::vector<int>& radices) {
+  for (int i = 0; i < kNumPlanes; ++i) {
+    const PlaneInfo& c = kPlanes[i];
+    if ((c.f64 != 0) == f64 && c.n == n && c.M == M && c.P == P && c.kf == kind_f && c.kb == kind_b &&
+        c.radices == radices)
+      return i;
+  }
+  return -1;
+}
+
+int num_planes() { return kNumPlanes; }
+
+void plane_shape(int i, int* f64, int* nt, int* n) {
+  *f64 = kPlanes[i].f64;
+  *nt = kPlanes[i].nt;
+  *n = kPlanes[i].n;
+}
+
+hipError_t launch_plane(int i, const PassArgs& a2, const PassArgs& a1, int inverse, int64_t planes, hipStream_t s) {
+  if (i < 0 || i >= kNumPlanes) return hipErrorInvalidValue;
+  return kPlanes[i].launch(a2, a1, inverse, planes, s);
 }
 
 hipError_t launch_line_pass(int cfg, const PassArgs& a, hipStream_t s) {

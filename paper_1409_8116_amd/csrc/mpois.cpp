@@ -42,6 +42,10 @@ hipError_t launch_line_pass_batch(int cfg, const BatchPassArgs& b, int blocks, s
 hipError_t launch_resid_batch(const BatchResidArgs& b, int blocks, hipStream_t s);
 hipError_t launch_proj_div(const ProjDev& q, double* g, hipStream_t s);
 hipError_t launch_proj_correct(const ProjDev& q, const void* phi, int f64, int mask, int add_p, hipStream_t s);
+int find_plane(bool f64, int n, int M, int P, int kind_f, int kind_b, const std::vector<int>& radices);
+int num_planes();
+void plane_shape(int i, int* f64, int* nt, int* n);
+hipError_t launch_plane(int i, const PassArgs& a2, const PassArgs& a1, int inverse, int64_t planes, hipStream_t s);
 hipError_t launch_finalize_batch(const double* partials, const int* blk_start, const int* blk_count,
                                  const double* inv_wsum, double* scalars, int count, hipStream_t s);
 }  // namespace mpois
@@ -335,11 +339,13 @@ struct Pass {
   int cfg = 0;    // generic kernel shape (cfgs.h); batches always use it
   int spec = -1;  // specialised kernel (specs.h) used by single-grid executes, or -1
   int axis = 0;   // axis this pass transforms
+  int table = -1; // index of its axis tables in the plan
 };
 
 // Kernel ids reported by mpois_profile: generic shapes 0.., residual 100,
 // reduction 101, specialised kernels kSpecBase + spec index.
 constexpr int kSpecBase = 200;
+constexpr int kPlaneBase = 300;  // plane kernels (planes.h)
 
 struct SubPlan {
   int ndim = 0;
@@ -354,6 +360,7 @@ struct SubPlan {
   std::vector<Pass> passes;     // forward ... fused ... inverse
   ResidArgs resid{};
   int rperm[3] = {0, 1, 2};     // residual axis e is padded axis rperm[e]
+  int plane = -1;               // plane kernel for the last two axes of a 3D grid, or -1
 };
 
 // Per-launch record of a profiled execute.
@@ -918,6 +925,7 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
       p.cfg = default_cfg(pl->f64work, int(n), int(shape.P), has_rader(shape), has_odd_large(shape));
     }
     a.ax = pl->tables[ti].dev;
+    p.table = ti;
     // C-contiguous addressing of src and dst (views override it per execute)
     a.src_vnb = a.dst_vnb = inner;
     a.src_va = a.dst_va = n * inner;
@@ -940,6 +948,18 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
   if (st != MPOIS_OK) return st;
   for (const Pass& p : sp->passes)
     if (p.cfg < 0) return MPOIS_ERR_UNSUPPORTED;
+  // both of the last two axes of a 3D grid in one plane sweep, when they share
+  // a transform a plane kernel is compiled for (MPOIS_NO_PLANE=1: never, a
+  // test hook comparing it with the per-axis sweeps)
+  const char* noplane = std::getenv("MPOIS_NO_PLANE");
+  if (D == 3 && !(noplane && noplane[0] == '1')) {
+    const AxisShape& s2 = pl->tables[sp->passes[0].table].shape;
+    const AxisShape& s1 = pl->tables[sp->passes[1].table].shape;
+    // one set of tables (the plane kernel stages one twiddle table for both)
+    if (sp->passes[0].table == sp->passes[1].table && sp->passes[3].table == sp->passes[4].table &&
+        g->n[1] == g->n[2] && s1.kind_f == s2.kind_f && s1.kind_b == s2.kind_b && !s2.bluestein)
+      sp->plane = find_plane(pl->f64work, int(g->n[2]), int(s2.M), int(s2.P), s2.kind_f, s2.kind_b, s2.radices);
+  }
   // residual description
   ResidArgs& r = sp->resid;
   for (int e = 0; e < 3; ++e) {
@@ -1089,6 +1109,36 @@ hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, 
                      const int64_t* in_view = nullptr, const int64_t* out_view = nullptr,
                      const int64_t* work_view = nullptr, const ProjDev* proj = nullptr) {
   const size_t np = sp.passes.size();
+  if (sp.plane >= 0 && !in_view && !out_view && !work_view && !proj) {
+    // forward planes (axes 2 and 1), the fused axis-0 sweep, inverse planes
+    const double pts = double(sp.npts);
+    PassArgs f2 = sp.passes[0].args, f1 = sp.passes[1].args;
+    f2.src = in;
+    f2.src_f64 = in_f64;
+    f1.dst = work;
+    f1.dst_f64 = work_f64;
+    hipError_t e = launch_plane(sp.plane, f2, f1, 0, sp.n[0], s);
+    if (e != hipSuccess) return e;
+    prof_mark(pl, kPlaneBase + sp.plane, pts * ((in_f64 ? 8 : 4) + (work_f64 ? 8 : 4)), s);
+    Pass& m = sp.passes[2];
+    PassArgs a = m.args;
+    a.src = a.dst = work;
+    a.src_f64 = a.dst_f64 = work_f64;
+    e = m.spec >= 0 ? launch_spec(m.spec, a, s) : launch_line_pass(m.cfg, a, s);
+    if (e != hipSuccess) return e;
+    prof_mark(pl, m.spec >= 0 ? kSpecBase + m.spec : m.cfg, pts * (work_f64 ? 16 : 8), s);
+    PassArgs i1 = sp.passes[3].args, i2 = sp.passes[4].args;
+    i1.src = work;
+    i1.src_f64 = work_f64;
+    i2.dst = out;
+    i2.dst_f64 = out_f64;
+    i2.update = update ? 1 : 0;
+    i2.shift = shift;
+    e = launch_plane(sp.plane, i2, i1, 1, sp.n[0], s);
+    if (e != hipSuccess) return e;
+    prof_mark(pl, kPlaneBase + sp.plane, pts * ((work_f64 ? 8 : 4) + (out_f64 ? 8 : 4) + (update ? 8 : 0)), s);
+    return hipSuccess;
+  }
   for (size_t i = 0; i < np; ++i) {
     Pass& p = sp.passes[i];
     PassArgs a = p.args;
@@ -1795,6 +1845,15 @@ mpois_status mpois_destroy(mpois_plan pl) {
 size_t mpois_workspace_bytes(mpois_plan pl) { return pl ? pl->bytes : 0; }
 
 mpois_status mpois_kernel_shape(int cfg, int* elem_bytes, int* pairs, int* threads, int* max_len) {
+  if (cfg >= kPlaneBase && cfg < kPlaneBase + num_planes()) {
+    int f64, nt, n;
+    plane_shape(cfg - kPlaneBase, &f64, &nt, &n);
+    if (elem_bytes) *elem_bytes = f64 ? 8 : 4;
+    if (pairs) *pairs = n / 2;
+    if (threads) *threads = nt;
+    if (max_len) *max_len = n;
+    return MPOIS_OK;
+  }
   if (cfg >= kSpecBase && cfg < kSpecBase + num_specs()) {
     int f64, np, nt, n;
     spec_shape(cfg - kSpecBase, &f64, &np, &nt, &n);

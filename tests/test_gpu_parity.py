@@ -165,6 +165,37 @@ def test_periodic_box_32():
     assert abs(out.mean()) <= 1e-14 * np.abs(out).max()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32r"])
+def test_plane_kernels_match_oracle_and_per_axis_sweeps(prec, monkeypatch):
+    """32 x 32 periodic planes in one sweep (three launches per solve): the
+    oracle on the 32^3 box and on a 7 x 32 x 32 box, the same results as the
+    per-axis sweeps (MPOIS_NO_PLANE=1), and the profile names the plane
+    kernels."""
+    mp = _mp()
+    for shape in ((32, 32, 32), (7, 32, 32)):
+        d, g = workloads.periodic_noise(32, seed=1)
+        g = g[: shape[0]] - g[: shape[0]].mean()
+        h = d["h"]
+        print(f"[parity] planes {prec} {shape}", flush=True)
+        ref = oracle_solve(g, shape, h, d["bc"], d["grid"], "fd")
+        out, info = gpu_solve(g, shape, h, d["bc"], d["grid"], "fd", prec)
+        assert rel_err(out, ref) <= TOL[prec], (shape, prec)
+        monkeypatch.setenv("MPOIS_NO_PLANE", "1")
+        per_axis, _ = gpu_solve(g, shape, h, d["bc"], d["grid"], "fd", prec)
+        monkeypatch.delenv("MPOIS_NO_PLANE")
+        assert rel_err(out, per_axis) <= (1e-6 if prec == "f32" else 1e-14), (shape, prec)
+    plan = mp.Plan((32, 32, 32), d["h"], d["bc"], d["grid"], prec=prec, profile=True)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    rhs = torch.zeros((32, 32, 32), dtype=dt, device="cuda")
+    plan.solve(rhs, torch.empty_like(rhs))
+    kernels = [r["kernel"] for r in plan.profile()]
+    plan.close()
+    line_kernels = [k for k in kernels if k not in (100, 101)]
+    planes = sum(k >= 300 for k in line_kernels)
+    # every solve: forward planes, the fused axis-0 sweep, inverse planes
+    assert planes > 0 and 3 * planes == 2 * len(line_kernels), kernels
+
+
 @pytest.mark.parametrize("approx,prec", [("fd", "f64"), ("ps", "f64"), ("fd", "f32"), ("ps", "f32")])
 def test_mixed_box_256(approx, prec):
     d, g, modes = workloads.mixed_modes(256, seed=2, approx=approx)
