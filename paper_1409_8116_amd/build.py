@@ -93,7 +93,9 @@ def build(verbose=False, jobs=None, incremental=False):
         raise RuntimeError("kernels that keep data in scratch memory (a demoted array or struct, or heavy "
                            "register spills): " + ", ".join(large))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    # roctx (rocprofiler-sdk) for the MPOIS_TRACE ranges
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -4,6 +4,7 @@
 #include "mpois.h"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -445,6 +446,23 @@ struct mpois_plan_s {
 };
 
 namespace {
+
+// Named ranges (roctx) around the library's calls and the phases of a solve,
+// for rocprofv3 --marker-trace, when the environment sets MPOIS_TRACE=1
+// (read on every call, so a process can switch it).
+struct TraceRange {
+  bool on;
+  explicit TraceRange(const char* name) {
+    const char* e = std::getenv("MPOIS_TRACE");
+    on = e && e[0] == '1';
+    if (on) roctxRangePushA(name);
+  }
+  ~TraceRange() {
+    if (on) roctxRangePop();
+  }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 bool fault_alloc() {
   const char* e = std::getenv("MPOIS_FAULT_ALLOC");
@@ -1108,6 +1126,7 @@ hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, 
                      int work_f64, bool update, const double* shift, hipStream_t s,
                      const int64_t* in_view = nullptr, const int64_t* out_view = nullptr,
                      const int64_t* work_view = nullptr, const ProjDev* proj = nullptr) {
+  TraceRange trace_("mpois: solve");
   const size_t np = sp.passes.size();
   if (sp.plane >= 0 && !in_view && !out_view && !work_view && !proj) {
     // forward planes (axes 2 and 1), the fused axis-0 sweep, inverse planes
@@ -1191,6 +1210,7 @@ Workspace plan_workspace(mpois_plan_s* pl) {
 hipError_t run_resid(mpois_plan_s* pl, SubPlan& sp, const void* rhs, const void* phi, void* r, int r_f64,
                      const double* mg, double* scalars, hipStream_t s, double* partials = nullptr,
                      const IoViews& views = IoViews()) {
+  TraceRange trace_("mpois: residual");
   ResidArgs a = sp.resid;
   for (int e = 0; e < 3; ++e) {
     if (views.phi) a.ps[e] = views.phi[sp.rperm[e]];
@@ -1326,6 +1346,7 @@ mpois_status build_batch(mpois_plan_s* pl) {
 // first pass reads `in`, last pass writes `out`, the others use `work`.
 hipError_t batch_solve(mpois_plan_s* pl, const void* const* in, int in_f64, void* const* out, int out_f64,
                        void* const* work, int work_f64, bool update, hipStream_t s) {
+  TraceRange trace_("mpois: batch solve");
   BatchState& B = pl->batch;
   const size_t np = B.passes.size();
   for (size_t p = 0; p < np; ++p) {
@@ -1351,6 +1372,7 @@ hipError_t batch_solve(mpois_plan_s* pl, const void* const* in, int in_f64, void
 
 hipError_t batch_resid(mpois_plan_s* pl, const void* const* phi, const void* const* g, void* const* r, bool use_mg,
                        hipStream_t s) {
+  TraceRange trace_("mpois: batch residual");
   BatchState& B = pl->batch;
   BatchResidArgs b{};
   b.args = static_cast<const ResidArgs*>(B.resid_args.p);
@@ -1402,7 +1424,11 @@ hipError_t enqueue_batch(mpois_plan_s* pl, hipStream_t s) {
 extern "C" {
 
 const char* mpois_status_string(mpois_status s) {
-  switch (s) {
+  // a C caller may pass any int: read the bits, not a (possibly out of
+  // range) enumerator
+  int v;
+  std::memcpy(&v, &s, sizeof v);
+  switch (v) {
     case MPOIS_OK: return "ok";
     case MPOIS_ERR_INVALID: return "invalid argument";
     case MPOIS_ERR_UNSUPPORTED: return "unsupported";
@@ -1444,11 +1470,13 @@ mpois_status mpois_axis_plan(int bc, int grid, int64_t n, int* kind_fwd, int* ki
 
 mpois_status mpois_plan_create(const mpois_grid_desc* grid, int approx, int prec, double rtol, int max_iter,
                                unsigned flags, mpois_plan* out) {
+  TraceRange trace_("mpois_plan_create");
   return create_common(grid, 1, approx, prec, rtol, max_iter, flags, out);
 }
 
 mpois_status mpois_plan_create_batch(const mpois_grid_desc* grids, int count, int approx, int prec, double rtol,
                                      int max_iter, unsigned flags, mpois_plan* out) {
+  TraceRange trace_("mpois_plan_create_batch");
   return create_common(grids, count, approx, prec, rtol, max_iter, flags, out);
 }
 
@@ -1471,6 +1499,7 @@ static mpois_status check_ptrs(const mpois_plan_s* pl, const SubPlan& sp, const 
 }
 
 mpois_status mpois_execute(mpois_plan pl, const void* rhs, void* phi, void* stream) {
+  TraceRange trace_("mpois_execute");
   if (!pl || pl->subs.size() != 1) return MPOIS_ERR_INVALID;
   SubPlan& sp = pl->subs[0];
   // the attribute queries are host calls: repeat them only for new pointers
@@ -1568,6 +1597,7 @@ static mpois_status view_strides(const SubPlan& sp, const int64_t* st, int64_t o
 
 mpois_status mpois_execute_view(mpois_plan pl, const void* rhs, const int64_t* rhs_strides, void* phi,
                                 const int64_t* phi_strides, void* stream) {
+  TraceRange trace_("mpois_execute_view");
   if (!pl || pl->subs.size() != 1 || !rhs || !phi || !rhs_strides || !phi_strides) return MPOIS_ERR_INVALID;
   SubPlan& sp = pl->subs[0];
   int64_t rs[3], ps[3], rext = 0, pext = 0;
@@ -1612,6 +1642,7 @@ mpois_status mpois_execute_view(mpois_plan pl, const void* rhs, const int64_t* r
 // divergence is formed into a plan buffer (allocated on the first call),
 // solved with refinement, and all of the correction runs afterwards.
 mpois_status mpois_project(mpois_plan pl, void* const* vel, void* p, double adt, void* phi, void* stream) {
+  TraceRange trace_("mpois_project");
   if (!pl || pl->subs.size() != 1 || pl->batched) return MPOIS_ERR_INVALID;
   SubPlan& sp = pl->subs[0];
   if (!vel || !p || !phi || !std::isfinite(adt) || !(adt > 0.0)) return MPOIS_ERR_INVALID;
@@ -1722,6 +1753,7 @@ static mpois_status scratch_address(int dev, void** out) {
 }
 
 mpois_status mpois_execute_noalloc(mpois_plan pl, const void* rhs, void* phi, void* stream) {
+  TraceRange trace_("mpois_execute_noalloc");
   if (!pl || pl->subs.size() != 1) return MPOIS_ERR_INVALID;
   SubPlan& sp = pl->subs[0];
   const size_t work_bytes = pl->prec == MPOIS_F32_REFINE ? size_t(sp.npts) * sizeof(float) : 0;
@@ -1755,6 +1787,7 @@ mpois_status mpois_execute_noalloc(mpois_plan pl, const void* rhs, void* phi, vo
 }
 
 mpois_status mpois_execute_batch(mpois_plan pl, const void* const* rhs, void* const* phi, void* stream) {
+  TraceRange trace_("mpois_execute_batch");
   if (!pl || !rhs || !phi) return MPOIS_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t count = pl->subs.size();
@@ -1789,6 +1822,7 @@ mpois_status mpois_execute_batch(mpois_plan pl, const void* const* rhs, void* co
 }
 
 mpois_status mpois_get_info(mpois_plan pl, void* stream, mpois_info* out) {
+  TraceRange trace_("mpois_get_info");
   if (!pl || !out) return MPOIS_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);
   mpois_info info{};

@@ -143,3 +143,20 @@ def test_single_and_batch_executes_keep_their_own_report():
     torch.cuda.synchronize()
     assert plan.info()["rel_resid"] < 1e-12
     assert torch.equal(out, out2)
+
+
+def test_trace_ranges_leave_results_unchanged(monkeypatch):
+    """MPOIS_TRACE=1 wraps the calls and solve phases in roctx ranges (for
+    rocprofv3 --marker-trace); the results are bit for bit the same."""
+    mp = _mp()
+    shape, h, bc, grid = (20, 24, 18), (0.05, 0.04, 0.06), ("P", "N", "D"), ("v", "s", "s")
+    g = torch.tensor(np.random.default_rng(7).standard_normal(shape), device="cuda")
+    outs = []
+    for trace in ("0", "1"):
+        monkeypatch.setenv("MPOIS_TRACE", trace)
+        plan = mp.Plan(shape, h, bc, grid, prec="f32r", max_iter=2)
+        outs.append(plan.solve(g).clone())
+        plan.info()
+        plan.close()
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
