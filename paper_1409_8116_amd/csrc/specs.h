@@ -32,9 +32,9 @@
   /* channel: 256-point periodic, 512-point staggered Neumann, 1024-point periodic */ \
   X(14, float, 8, 512, 0, 1, 1, 256, 256, 256, 0, -1, 16, 16)        \
   X(15, float, 8, 512, 0, 1, 1, 256, 256, 256, 1, -1, 16, 16)        \
-  X(16, float, 8, 512, 0, 1, 1, 512, 512, 512, 2, -1, 32, 16)        \
-  X(17, float, 8, 512, 0, 1, 1, 512, 512, 512, 3, -1, 32, 16)        \
-  X(18, float, 4, 512, 0, 1, 1, 1024, 1024, 1024, 0, 1, 32, 32)      \
+  X(16, float, 16, 512, 0, 1, 1, 512, 512, 512, 2, -1, 32, 16)        \
+  X(17, float, 16, 512, 0, 1, 1, 512, 512, 512, 3, -1, 32, 16)        \
+  X(18, float, 8, 512, 0, 1, 1, 1024, 1024, 1024, 0, 1, 32, 32)      \
   /* 32-point periodic (FP64) */                                   \
   X(19, double, 8, 512, 0, 1, 1, 32, 32, 32, 0, -1, 8, 4)            \
   X(20, double, 8, 512, 0, 1, 1, 32, 32, 32, 0, 1, 8, 4)             \
