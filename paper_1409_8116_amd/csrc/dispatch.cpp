@@ -17,7 +17,7 @@ namespace mpois {
   hipError_t prepare_line_pass_cfg##I();
 MPOIS_DECL(0) MPOIS_DECL(1) MPOIS_DECL(2) MPOIS_DECL(3) MPOIS_DECL(4) MPOIS_DECL(5) MPOIS_DECL(6)
 MPOIS_DECL(7) MPOIS_DECL(8) MPOIS_DECL(9) MPOIS_DECL(10) MPOIS_DECL(11) MPOIS_DECL(12) MPOIS_DECL(13)
-MPOIS_DECL(14) MPOIS_DECL(15)
+MPOIS_DECL(14) MPOIS_DECL(15) MPOIS_DECL(16) MPOIS_DECL(17)
 #undef MPOIS_DECL
 
 // one pair per specialised kernel, defined in sp_inst.hip compiled with MPOIS_SPEC = id
@@ -72,13 +72,13 @@ const KernelCfg kCfgs[] = {
 };
 constexpr int kNum = sizeof(kCfgs) / sizeof(kCfgs[0]);
 static_assert(kNum == MPOIS_NUM_CFGS, "shape list and count disagree");
-static_assert(kNum == 16, "update the per-shape function tables below");
+static_assert(kNum == 18, "update the per-shape function tables below");
 
 using LaunchFn = hipError_t (*)(const PassArgs&, hipStream_t, size_t);
 using LaunchBatchFn = hipError_t (*)(const BatchPassArgs&, int, hipStream_t, size_t);
 using PrepareFn = hipError_t (*)();
 #define MPOIS_ROW(F) \
-  F##0, F##1, F##2, F##3, F##4, F##5, F##6, F##7, F##8, F##9, F##10, F##11, F##12, F##13, F##14, F##15
+  F##0, F##1, F##2, F##3, F##4, F##5, F##6, F##7, F##8, F##9, F##10, F##11, F##12, F##13, F##14, F##15, F##16, F##17
 const LaunchFn kLaunch[kNum] = {MPOIS_ROW(launch_line_pass_cfg)};
 const LaunchBatchFn kLaunchBatch[kNum] = {MPOIS_ROW(launch_line_pass_batch_cfg)};
 const PrepareFn kPrepare[kNum] = {MPOIS_ROW(prepare_line_pass_cfg)};

@@ -698,10 +698,26 @@ __device__ __forceinline__ void dft_engine(cx<T>* Z, int P, int nstages, const S
       case 8: stage<T, 8, NP, NT, PMAX>(Z, P, st.ns, t); break;
       case 9: stage<T, 9, NP, NT, PMAX>(Z, P, st.ns, t); break;
       case 11:
-        if constexpr (SLIM == 0) stage<T, 11, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (SLIM != 1) stage<T, 11, NP, NT, PMAX>(Z, P, st.ns, t);
         break;
       case 13:
-        if constexpr (SLIM == 0) stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (SLIM != 1) stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t);
+        break;
+      // primes 17..31: only in the wide shapes (SLIM == 2)
+      case 17:
+        if constexpr (SLIM == 2) stage<T, 17, NP, NT, PMAX>(Z, P, st.ns, t);
+        break;
+      case 19:
+        if constexpr (SLIM == 2) stage<T, 19, NP, NT, PMAX>(Z, P, st.ns, t);
+        break;
+      case 23:
+        if constexpr (SLIM == 2) stage<T, 23, NP, NT, PMAX>(Z, P, st.ns, t);
+        break;
+      case 29:
+        if constexpr (SLIM == 2) stage<T, 29, NP, NT, PMAX>(Z, P, st.ns, t);
+        break;
+      case 31:
+        if constexpr (SLIM == 2) stage<T, 31, NP, NT, PMAX>(Z, P, st.ns, t);
         break;
       case 14:
         // only after a Rader stage (1022 = 73 x 14): one LDS sweep instead of 7 and 2
@@ -1478,13 +1494,13 @@ __device__ __forceinline__ void line_pass_body(const PassArgs& a, int64_t tile, 
 
 
 // Waves per SIMD the compiler must leave room for: 4 for slim shapes (two
-// Waves per SIMD the compiler must leave room for: 4 for slim shapes (two
 // 512-thread workgroups per CU, at most 128 registers per thread), 2 for
-// shapes with the Rader stage (at most 256 registers, so that a second
-// workgroup can hide the first one's global memory latency), else 1.
+// shapes with the Rader stage and the wide shapes (at most 256 registers, so
+// that a second workgroup can hide the first one's global memory latency),
+// else 1.
 template <int SLIM, int RADER>
 struct MinWaves {
-  static constexpr int v = SLIM ? 4 : (RADER ? 2 : 1);
+  static constexpr int v = SLIM == 1 ? 4 : ((RADER || SLIM == 2) ? 2 : 1);
 };
 
 // The batched kernel of a full (non-slim, non-Rader) FP32 shape: held to 128
@@ -1493,7 +1509,7 @@ struct MinWaves {
 // 512-thread workgroup per CU.  (The FP64 ones would spill.)
 template <typename T, int SLIM, int RADER>
 struct MinWavesBatch {
-  static constexpr int v = RADER ? 2 : (SLIM || sizeof(T) == 4) ? 4 : 1;
+  static constexpr int v = (RADER || SLIM == 2) ? 2 : (SLIM == 1 || sizeof(T) == 4) ? 4 : 1;
 };
 
 // One grid: block b owns tile b.

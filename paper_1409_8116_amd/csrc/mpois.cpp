@@ -173,10 +173,10 @@ bool factor_radices(int64_t M, bool f64, bool exact, std::vector<int>* out, int 
     m /= kRaderPrime;
   }
   // Bluestein lengths are chosen 7-smooth, so they run in every kernel shape
-  static const int kOddExact[] = {9, 3, 5, 7, 11, 13};
+  static const int kOddExact[] = {9, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
   static const int kOddSmooth[] = {9, 3, 5, 7};
   const int* odd = exact ? kOddExact : kOddSmooth;
-  const int nodd = exact ? 6 : 4;
+  const int nodd = exact ? 11 : 4;
   for (int oi = 0; oi < nodd; ++oi) {
     const int r = odd[oi];
     while (m % r == 0) {
@@ -286,7 +286,7 @@ std::vector<AxisShape> axis_variants(int bc, int grid, int64_t n, bool f64) {
     if (factor_radices(d.P, f64, !d.bluestein, &x.radices, 1)) add(x);
   }
   bool big_odd = false;
-  for (int r : d.radices) big_odd = big_odd || r == kRaderPrime || r == 11 || r == 13;
+  for (int r : d.radices) big_odd = big_odd || r == kRaderPrime || ((r & 1) && r >= 11);
   if (!d.bluestein && big_odd && d.M > 1) {
     AxisShape b = d;
     b.bluestein = true;
@@ -304,11 +304,14 @@ bool has_rader(const AxisShape& s) {
   return false;
 }
 
-// Radix 11 or 13: only the full (non-slim) kernel shapes have those codelets.
-bool has_odd_large(const AxisShape& s) {
+// Odd radices above 9 the plan needs: 0 none, 1 radix 11 or 13 (codelets in
+// the full and the wide shapes, not in the slim ones), 2 a prime 17..31
+// (codelets in the wide shapes only).
+int odd_class(const AxisShape& s) {
+  int c = 0;
   for (int r : s.radices)
-    if (r == 11 || r == 13) return true;
-  return false;
+    if ((r & 1) && r >= 11 && r != kRaderPrime) c = std::max(c, r >= 17 ? 2 : 1);
+  return c;
 }
 
 // ---------------------------------------------------------------------------- device tables
@@ -636,27 +639,28 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
 // Kernel configuration for a line pass.  Candidates: shapes of the working
 // precision that hold the work length in LDS and have the codelets the stage
 // list needs (the Rader stage only in RADER shapes; radix 11/13 only in
-// non-slim shapes).  Preference: slim shapes that fit two workgroups per CU
+// non-slim shapes, primes 17..31 only in the wide shapes).  Preference: slim shapes that fit two workgroups per CU
 // (LDS <= 80 KB), then the widest tile; with a Rader stage, 256 threads and
 // the narrowest tile.  MPOIS_FLAG_TUNE replaces this guess
 // by a measurement.
-bool cfg_fits(int i, bool f64, int n, int P, bool rader, bool odd) {
+bool cfg_fits(int i, bool f64, int n, int P, bool rader, int odd) {
   int cf64, np, nt, pmax;
   kernel_cfg(i, &cf64, &np, &nt, &pmax);
   if ((cf64 != 0) != f64 || P > pmax) return false;
   if (rader && !kernel_cfg_rader(i)) return false;
-  if (odd && kernel_cfg_slim(i)) return false;
+  if (odd >= 1 && kernel_cfg_slim(i) == 1) return false;
+  if (odd == 2 && kernel_cfg_slim(i) != 2) return false;
   return line_pass_lds(i, n, P) <= size_t(kMaxLds);
 }
 
-int default_cfg(bool f64, int n, int P, bool rader, bool odd) {
+int default_cfg(bool f64, int n, int P, bool rader, int odd) {
   int best = -1;
   long best_score = -1;
   for (int i = 0; i < num_kernel_cfgs(); ++i) {
     if (!cfg_fits(i, f64, n, P, rader, odd)) continue;
     int cf64, np, nt, pmax;
     kernel_cfg(i, &cf64, &np, &nt, &pmax);
-    const bool two = kernel_cfg_slim(i) && line_pass_lds(i, n, P) <= size_t(kMaxLds / 2);
+    const bool two = kernel_cfg_slim(i) == 1 && line_pass_lds(i, n, P) <= size_t(kMaxLds / 2);
     // a Rader stage keeps many values per lane: smaller workgroups and tiles
     // leave the registers to it (measured fastest on 512^3 DCT-I passes)
     // ties go to the smaller work-length bound (fewer guarded unrolled steps)
@@ -712,7 +716,7 @@ mpois_status validate_one(const mpois_grid_desc* g, int approx, int prec, int ma
   // every axis must fit one of the kernel shapes
   for (int d = 0; d < g->ndim; ++d) {
     AxisShape s = plan_axis_shape(axis_code(g->bc[d][0], g->bc[d][1]), g->grid[d], g->n[d], prec == MPOIS_F64);
-    if (default_cfg(prec == MPOIS_F64, int(g->n[d]), int(s.P), has_rader(s), has_odd_large(s)) < 0)
+    if (default_cfg(prec == MPOIS_F64, int(g->n[d]), int(s.P), has_rader(s), odd_class(s)) < 0)
       return MPOIS_ERR_UNSUPPORTED;
   }
   return MPOIS_OK;
@@ -789,12 +793,12 @@ int tune_axis_pass(mpois_plan_s* pl, const PassArgs& proto, int bc, int grid, in
   if (batch) {
     int pc = 0;
     while ((int64_t(1) << pc) < d0.P) ++pc;
-    const char* fam = has_rader(d0) ? "r" : has_odd_large(d0) ? "o" : d0.bluestein ? "b" : "s";
+    const char* fam = has_rader(d0) ? "r" : odd_class(d0) ? "o" : d0.bluestein ? "b" : "s";
     key += std::string("/tput/") + fam + std::to_string(pc) + "/";
     // and how many workgroups of each shape fit a CU (LDS) at this length:
     // members of a bucket then see the same occupancy per shape
     for (int c = 0; c < num_kernel_cfgs(); ++c) {
-      const bool fits = cfg_fits(c, f64, int(n), int(d0.P), has_rader(d0), has_odd_large(d0));
+      const bool fits = cfg_fits(c, f64, int(n), int(d0.P), has_rader(d0), odd_class(d0));
       const size_t lds = line_pass_lds(c, int(n), int(d0.P));
       key += fits ? char('0' + std::min<size_t>(4, size_t(kMaxLds) * 2 / std::max<size_t>(lds, 1) / 2)) : '-';
     }
@@ -814,8 +818,8 @@ int tune_axis_pass(mpois_plan_s* pl, const PassArgs& proto, int bc, int grid, in
     for (size_t i = 0; i < vars.size(); ++i)
       if (vars[i].tag == tag) v = i;
     const AxisShape& sh = vars[v];
-    const bool fits = ci >= 0 && cfg_fits(ci, f64, int(n), int(sh.P), has_rader(sh), has_odd_large(sh));
-    *cfg = fits ? ci : default_cfg(f64, int(n), int(sh.P), has_rader(sh), has_odd_large(sh));
+    const bool fits = ci >= 0 && cfg_fits(ci, f64, int(n), int(sh.P), has_rader(sh), odd_class(sh));
+    *cfg = fits ? ci : default_cfg(f64, int(n), int(sh.P), has_rader(sh), odd_class(sh));
     if (*cfg < 0) return -1;
     return table_for(pl, bc, grid, n, sh, st);
   }
@@ -831,7 +835,7 @@ int tune_axis_pass(mpois_plan_s* pl, const PassArgs& proto, int bc, int grid, in
     PassArgs a = proto;
     a.ax = pl->tables[t].dev;
     for (int c = 0; c < num_kernel_cfgs(); ++c) {
-      if (!cfg_fits(c, f64, int(n), int(sh.P), has_rader(sh), has_odd_large(sh))) continue;
+      if (!cfg_fits(c, f64, int(n), int(sh.P), has_rader(sh), odd_class(sh))) continue;
       int cf64, np, nt, pmax;
       kernel_cfg(c, &cf64, &np, &nt, &pmax);
       int64_t lines = proto.nlines;
@@ -856,7 +860,7 @@ int tune_axis_pass(mpois_plan_s* pl, const PassArgs& proto, int bc, int grid, in
   if (std::getenv("MPOIS_LOG"))
     std::fprintf(stderr, "[mpois tune] %s n%lld -> plan tag %d shape %d (untuned shape %d)\n", key.c_str(),
                  static_cast<long long>(n), best_tag, ci,
-                 default_cfg(f64, int(n), int(d0.P), has_rader(d0), has_odd_large(d0)));
+                 default_cfg(f64, int(n), int(d0.P), has_rader(d0), odd_class(d0)));
   if (only < 0) tune_store(key, best_tag, ci);
   *cfg = ci;
   return best_t;
@@ -940,7 +944,7 @@ mpois_status build_sub(mpois_plan_s* pl, const mpois_grid_desc* g, SubPlan* sp) 
     if (ti < 0) {
       ti = table_for(pl, bc, grd, n, shape, &st);
       if (st != MPOIS_OK) return p;
-      p.cfg = default_cfg(pl->f64work, int(n), int(shape.P), has_rader(shape), has_odd_large(shape));
+      p.cfg = default_cfg(pl->f64work, int(n), int(shape.P), has_rader(shape), odd_class(shape));
     }
     a.ax = pl->tables[ti].dev;
     p.table = ti;

@@ -75,8 +75,11 @@ def check(shape, kinds, approx, prec, seed=0, h=None, max_iter=2, shift=0.0):
 # ------------------------------------------------------------------ 1D: every kind, many lengths
 # Rader stage then Stockham stages: DST-I n = 72 and DCT-I n = 74 (146 = 73 x 2), DCT-I n = 147
 # (292 = 73 x 4) and n = 439 (876 = 73 x 12); DCT-I n = 512: 1022 = 73 x 14 (the radix-14 stage)
-LENGTHS = [1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 12, 13, 16, 17, 25, 31, 32, 37, 49, 64, 72, 74, 100, 121, 127, 128, 143,
-           147, 169, 255, 256, 257, 343, 439, 509, 511, 512, 513, 1000, 1021, 1024]
+# includes lengths whose DFTs take the prime codelets 17..31 of the wide shapes
+# (19, 23, 29, 38 = 2*19, 46, 58, 62, 341 = 11*31, 527 = 17*31, 986 = 2*17*29)
+LENGTHS = [1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 12, 13, 16, 17, 19, 23, 25, 29, 31, 32, 37, 38, 46, 49, 58, 62, 64, 72, 74,
+           100, 121, 127, 128, 143, 147, 169, 255, 256, 257, 341, 343, 439, 509, 511, 512, 513, 527, 986, 1000, 1021,
+           1024]
 
 
 @pytest.mark.parametrize("kind", KINDS)
