@@ -109,6 +109,90 @@ __device__ __forceinline__ int64_t xcd_unit(int64_t b, int64_t G) {
   return x * q + (x < r ? x : r) + i;
 }
 
+// The same residual two points per thread along axis 2 (16-byte loads of
+// phi and g, one 8-byte load for each end of the pair): fewer, wider
+// requests for the same bytes.  Needs an even n2, unit strides along axis 2,
+// even strides elsewhere and 16-byte aligned phi and g (checked by the
+// caller).  A unit is a strip of 2 RESID_NT points; the blocks beyond the
+// unit count stay idle.
+__device__ __forceinline__ void resid_pairs(const ResidArgs& a, int64_t blk, int64_t nblk, double mg, double* s_wphi,
+                                            double* s_wg, double* s_r2, double* s_g2) {
+  const int64_t n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  constexpr int W = 2 * RESID_NT;
+  const int64_t strips = (n2 + W - 1) / W;
+  const int64_t segs = (n0 + RESID_SEG - 1) / RESID_SEG;
+  const int64_t units = strips * n1 * segs;
+  const int64_t G = nblk < units ? nblk : units;
+  if (blk >= G) return;
+  const int64_t plane = n1 * n2;
+  const double* __restrict__ phi = a.phi;
+  const double* __restrict__ g = a.g;
+  double* __restrict__ r64 = a.r && a.r_f64 ? static_cast<double*>(a.r) : nullptr;
+  float* __restrict__ r32 = a.r && !a.r_f64 ? static_cast<float*>(a.r) : nullptr;
+  for (int64_t u = xcd_unit(blk, G); u < units; u += G) {
+    const int64_t seg = u / (strips * n1);
+    const int64_t rem = u - seg * strips * n1;
+    const int64_t i1 = rem / strips;
+    const int64_t i2 = (rem - i1 * strips) * W + 2 * int64_t(threadIdx.x);
+    if (i2 >= n2) continue;
+    const int64_t p0 = a.ps[0], g0 = a.gs[0];
+    const int64_t base = i1 * n2 + i2;
+    const double w1 = axis_weight(a.clo[1], a.chi[1], i1, n1);
+    const double wa = w1 * axis_weight(a.clo[2], a.chi[2], i2, n2);
+    const double wb = w1 * axis_weight(a.clo[2], a.chi[2], i2 + 1, n2);
+    // low end of point a and high end of point b (the pair's inner
+    // neighbours are each other)
+    const Neighbours qa = neighbours(i2, n2, 1, a.clo[2], a.chi[2]);
+    const Neighbours qb = neighbours(i2 + 1, n2, 1, a.clo[2], a.chi[2]);
+    const Neighbours q1 = neighbours(i1, n1, a.ps[1], a.clo[1], a.chi[1]);
+    const double* __restrict__ pp = phi + i1 * a.ps[1] + i2;
+    const double* __restrict__ gp = g + i1 * a.gs[1] + i2;
+    auto ld2 = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
+    const double2 first = ld2(pp);
+    const double2 last = ld2(pp + (n0 - 1) * p0);
+    const int64_t s0 = seg * RESID_SEG;
+    const int64_t s1 = (s0 + RESID_SEG < n0) ? s0 + RESID_SEG : n0;
+    double2 prev = s0 > 0 ? ld2(pp + (s0 - 1) * p0) : double2{0.0, 0.0};
+    double2 cur = ld2(pp + s0 * p0);
+    double2 next = s0 + 1 < n0 ? ld2(pp + (s0 + 1) * p0) : cur;
+    int64_t o = s0 * p0, og = s0 * g0, orr = s0 * plane;
+#pragma unroll 2
+    for (int64_t i0 = s0; i0 < s1; ++i0, o += p0, og += g0, orr += plane) {
+      const double2 gv = ld2(gp + og);
+      const double left = pp[o + qa.dlo], right = pp[o + 1 + qb.dhi];
+      const double2 dn = ld2(pp + o + q1.dlo), up = ld2(pp + o + q1.dhi);
+      const double d2a = qa.alo * left + qa.blo * cur.x - 2.0 * cur.x + cur.y;
+      const double d2b = cur.x - 2.0 * cur.y + qb.ahi * right + qb.bhi * cur.y;
+      const double d1a = q1.alo * dn.x + q1.blo * cur.x - 2.0 * cur.x + q1.ahi * up.x + q1.bhi * cur.x;
+      const double d1b = q1.alo * dn.y + q1.blo * cur.y - 2.0 * cur.y + q1.ahi * up.y + q1.bhi * cur.y;
+      const double d0a = second_diff_reg(prev.x, cur.x, next.x, i0, n0, a.clo[0], a.chi[0], last.x, first.x);
+      const double d0b = second_diff_reg(prev.y, cur.y, next.y, i0, n0, a.clo[0], a.chi[0], last.y, first.y);
+      const double la = a.inv_h2[2] * d2a + a.inv_h2[1] * d1a + a.inv_h2[0] * d0a - a.shift * cur.x;
+      const double lb = a.inv_h2[2] * d2b + a.inv_h2[1] * d1b + a.inv_h2[0] * d0b - a.shift * cur.y;
+      const double gca = gv.x - mg, gcb = gv.y - mg;
+      const double ra = gca - la, rb = gcb - lb;
+      if (r64) *reinterpret_cast<double2*>(r64 + base + orr) = double2{ra, rb};
+      else if (r32) *reinterpret_cast<float2*>(r32 + base + orr) = float2{float(ra), float(rb)};
+      const double w0 = axis_weight(a.clo[0], a.chi[0], i0, n0);
+      *s_wphi += w0 * (wa * cur.x + wb * cur.y);
+      *s_wg += w0 * (wa * gv.x + wb * gv.y);
+      *s_r2 += ra * ra + rb * rb;
+      *s_g2 += gca * gca + gcb * gcb;
+      prev = cur;
+      cur = next;
+      next = (i0 + 2 < n0) ? ld2(pp + o + 2 * p0) : cur;
+    }
+  }
+}
+
+// Whether the two-point path applies (uniform for the launch).
+__device__ __forceinline__ bool resid_pairs_ok(const ResidArgs& a) {
+  const uintptr_t al = reinterpret_cast<uintptr_t>(a.phi) | reinterpret_cast<uintptr_t>(a.g) |
+                       (a.r ? reinterpret_cast<uintptr_t>(a.r) : 0);
+  return a.phi && a.n[2] >= 2 && a.n[2] % 2 == 0 && a.ps[2] == 1 && a.gs[2] == 1 &&
+         ((a.ps[0] | a.ps[1] | a.gs[0] | a.gs[1]) & 1) == 0 && (al & 15) == 0;
+}
+
 __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int64_t nblk, double* part) {
   const int64_t n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
   const int64_t strips = (n2 + RESID_NT - 1) / RESID_NT;
@@ -138,8 +222,10 @@ __device__ __forceinline__ void resid_body(const ResidArgs& a, int64_t blk, int6
       }
     }
   }
+  const bool pairs = resid_pairs_ok(a);
+  if (pairs) resid_pairs(a, blk, nblk, mg, &s_wphi, &s_wg, &s_r2, &s_g2);
   // distinct arrays: the loads of later planes may move above the stores of r
-  const double* __restrict__ phi = a.phi;
+  const double* __restrict__ phi = pairs ? nullptr : a.phi;
   const double* __restrict__ g = a.g;
   double* __restrict__ r64 = a.r && a.r_f64 ? static_cast<double*>(a.r) : nullptr;
   float* __restrict__ r32 = a.r && !a.r_f64 ? static_cast<float*>(a.r) : nullptr;
