@@ -348,6 +348,13 @@ def run_channel(args):
            "points_per_s": npts / (ms * 1e-3), "hbm_gbs_step": step_gbs(recs, reps, ms),
            "roofline": kernel_roofline(recs, reps), "rel_resid_worst_sampled": worst_resid}
     log(f"[channel] {ms:.3f} ms per right-hand side, {out['hbm_gbs_step']:.0f} GB/s")
+    # the plain FP64 path on the same stream buffer, for comparison
+    plan64 = mp.Plan.from_desc(d, prec="f64")
+    phi64 = torch.empty_like(rhs)
+    ms64, _ = timed(lambda: plan64.solve(rhs, phi64), max(args.steps, 10), args.warmup)
+    plan64.close()
+    out["fp64_ms_per_rhs"] = ms64
+    log(f"[channel] FP64 path {ms64:.3f} ms per right-hand side")
     if not args.no_cpu:
         ref, dt, threads = cpu_oracle(d, g0.cpu().numpy())
         out["rel_err_vs_oracle_rhs0"] = rel(first, ref)

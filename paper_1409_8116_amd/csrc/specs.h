@@ -38,6 +38,12 @@
   /* 32-point periodic (FP64) */                                   \
   X(19, double, 8, 512, 0, 1, 1, 32, 32, 32, 0, -1, 8, 4)            \
   X(20, double, 8, 512, 0, 1, 1, 32, 32, 32, 0, 1, 8, 4)             \
-  X(21, double, 8, 512, 0, 1, 1, 32, 32, 32, 1, -1, 8, 4)
+  X(21, double, 8, 512, 0, 1, 1, 32, 32, 32, 1, -1, 8, 4)            \
+  /* channel in FP64 (the projection step's FP64 plans) */         \
+  X(22, double, 8, 512, 0, 1, 1, 256, 256, 256, 0, -1, 16, 16)       \
+  X(23, double, 8, 512, 0, 1, 1, 256, 256, 256, 1, -1, 16, 16)       \
+  X(24, double, 8, 512, 0, 1, 1, 512, 512, 512, 2, -1, 8, 8, 8)      \
+  X(25, double, 8, 512, 0, 1, 1, 512, 512, 512, 3, -1, 8, 8, 8)      \
+  X(26, double, 4, 512, 0, 1, 0, 1024, 1024, 1024, 0, 1, 16, 8, 8)
 
-#define MPOIS_NUM_SPECS 22
+#define MPOIS_NUM_SPECS 27
