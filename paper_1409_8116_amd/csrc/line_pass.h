@@ -1579,6 +1579,16 @@ line_pass_spec(PassArgs a) {
       a, xcd_tile(blockIdx.x, gridDim.x), smem);
 }
 
+// The same with the projection-step loads and stores (first and last sweeps
+// of a projection step; instantiated for the unfused kernels only).
+template <typename T, int NP, int NT, int RADER, int SLIM, int PAD, int N, int M, int P, int KF, int KB, int... Rs>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MinWaves<SLIM, RADER>::v, 8)))
+line_pass_spec_proj(PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  line_pass_body<T, NP, NT, P, RADER, SLIM, Ax<N, M, P>, KF, KB, StageList<Rs...>, NP + PAD, true>(
+      a, xcd_tile(blockIdx.x, gridDim.x), smem);
+}
+
 template <typename T, int NP, int NT, int RADER, int SLIM, int PAD, int N, int M, int P, int KF, int KB, int... Rs>
 hipError_t launch_spec_t(const PassArgs& a, hipStream_t s, size_t lds) {
   constexpr int64_t TL = 2 * NP;
@@ -1586,13 +1596,27 @@ hipError_t launch_spec_t(const PassArgs& a, hipStream_t s, size_t lds) {
       a.ax.nstages != int(sizeof...(Rs)))
     return hipErrorInvalidValue;  // the description must be the one this kernel was compiled for
   const int64_t blocks = (a.nlines + TL - 1) / TL;
-  hipLaunchKernelGGL((line_pass_spec<T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, Rs...>), dim3(unsigned(blocks)),
-                     dim3(NT), lds, s, a);
+  if (a.proj_load || a.proj_store) {
+    if constexpr (KB < 0)
+      hipLaunchKernelGGL((line_pass_spec_proj<T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, Rs...>),
+                         dim3(unsigned(blocks)), dim3(NT), lds, s, a);
+    else
+      return hipErrorInvalidValue;  // fused kernels carry no projection I/O
+  } else {
+    hipLaunchKernelGGL((line_pass_spec<T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, Rs...>), dim3(unsigned(blocks)),
+                       dim3(NT), lds, s, a);
+  }
   return hipGetLastError();
 }
 
 template <typename T, int NP, int NT, int RADER, int SLIM, int PAD, int N, int M, int P, int KF, int KB, int... Rs>
 hipError_t prepare_spec_t() {
+  if constexpr (KB < 0) {
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&line_pass_spec_proj<T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, Rs...>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
   return hipFuncSetAttribute(
       reinterpret_cast<const void*>(&line_pass_spec<T, NP, NT, RADER, SLIM, PAD, N, M, P, KF, KB, Rs...>),
       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

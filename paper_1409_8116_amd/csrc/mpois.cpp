@@ -1188,8 +1188,9 @@ hipError_t run_solve(mpois_plan_s* pl, SubPlan& sp, const void* in, int in_f64, 
     }
     // the specialised kernels take the contiguous tile paths when they can, and
     // their generic path otherwise (views included)
-    // (the projection loads and stores exist in the generic kernels only)
-    const bool spec = p.spec >= 0 && !(a.proj_load || a.proj_store);
+    // (the projection loads and stores exist in the generic kernels and the
+    // unfused specialised ones)
+    const bool spec = p.spec >= 0 && !((a.proj_load || a.proj_store) && a.kind_b >= 0);
     hipError_t e = spec ? launch_spec(p.spec, a, s) : launch_line_pass(p.cfg, a, s);
     if (e != hipSuccess) return e;
     const double pts = double(sp.npts);

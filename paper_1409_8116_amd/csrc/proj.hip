@@ -16,128 +16,131 @@ namespace {
 
 constexpr int PROJ_NT = 256;
 
-// Index arithmetic in 32 bits when the array allows it.
-template <typename I>
-__device__ __forceinline__ void unflatten(I i, const I s[3], I c[3]) {
-  c[2] = i % s[2];
-  const I r = i / s[2];
-  c[1] = r % s[1];
-  c[0] = r / s[1];
-}
+// The kernels walk rows along the contiguous axis: a block takes rows
+// (c0, c1) in turn (one division per row) and its threads the elements of the
+// row, so every access is coalesced and the per-element index work is an add.
 
 // g[c] = div(vel)[c] / adt for every cell (C order).
-template <typename I>
-__device__ void div_cells(const ProjDev& q, double* g) {
-  const I s[3] = {I(q.n[0]), I(q.n[1]), I(q.n[2])};
-  const I total = s[0] * s[1] * s[2];
-  for (I i = I(blockIdx.x) * PROJ_NT + threadIdx.x; i < total; i += I(gridDim.x) * PROJ_NT) {
-    I c[3];
-    unflatten(i, s, c);
-    double sum = 0.0;
-#pragma unroll
+__global__ void __launch_bounds__(PROJ_NT) proj_div_kernel(ProjDev q, double* g) {
+  const int64_t n0 = q.n[0], n1 = q.n[1], n2 = q.n[2];
+  for (int64_t row = blockIdx.x; row < n0 * n1; row += gridDim.x) {
+    const int64_t c0 = row / n1, c1 = row - c0 * n1;
+    int64_t base[3], step[3];
     for (int d = 0; d < 3; ++d) {
-      const double* u = static_cast<const double*>(q.vel[d]);
-      if (!u) continue;
-      const I vd = I(q.vs[d][d]);
-      const I o = c[0] * I(q.vs[d][0]) + c[1] * I(q.vs[d][1]) + c[2] * I(q.vs[d][2]);
-      const I up = (q.ext[d] == 0 && c[d] + 1 == s[d]) ? o - (s[d] - 1) * vd : o + vd;
-      sum += (u[up] - u[o]) * q.inv_h[d];
+      base[d] = c0 * q.vs[d][0] + c1 * q.vs[d][1];
+      step[d] = q.vs[d][d];
     }
-    g[i] = sum * q.inv_adt;
+    // the face above cell c along axes 0 / 1 (fixed for the row)
+    const int64_t up0 = (q.ext[0] == 0 && c0 + 1 == n0) ? -(n0 - 1) * step[0] : step[0];
+    const int64_t up1 = (q.ext[1] == 0 && c1 + 1 == n1) ? -(n1 - 1) * step[1] : step[1];
+    const double* u0 = static_cast<const double*>(q.vel[0]);
+    const double* u1 = static_cast<const double*>(q.vel[1]);
+    const double* u2 = static_cast<const double*>(q.vel[2]);
+    for (int64_t c2 = threadIdx.x; c2 < n2; c2 += PROJ_NT) {
+      double sum = 0.0;
+      if (u0) {
+        const int64_t o = base[0] + c2;
+        sum += (u0[o + up0] - u0[o]) * q.inv_h[0];
+      }
+      if (u1) {
+        const int64_t o = base[1] + c2;
+        sum += (u1[o + up1] - u1[o]) * q.inv_h[1];
+      }
+      if (u2) {
+        const int64_t o = base[2] + c2;
+        const int64_t up2 = (q.ext[2] == 0 && c2 + 1 == n2) ? -(n2 - 1) : 1;
+        sum += (u2[o + up2] - u2[o]) * q.inv_h[2];
+      }
+      g[row * n2 + c2] = sum * q.inv_adt;
+    }
   }
-}
-
-__global__ void __launch_bounds__(PROJ_NT) proj_div_kernel(ProjDev q, double* g, int wide) {
-  if (wide) div_cells<int64_t>(q, g);
-  else div_cells<uint32_t>(q, g);
 }
 
 // Component d (blockIdx.y < 3, when bit d of mask is set): u_d -= adt grad_d phi
 // on every face; blockIdx.y == 3 (when add_p): p += phi.
-template <typename D, typename I>
-__device__ void correct(const ProjDev& q, const D* phi, int mask, int add_p) {
+template <typename D>
+__global__ void __launch_bounds__(PROJ_NT) proj_correct_kernel(ProjDev q, const D* phi, int mask, int add_p) {
   const int d = int(blockIdx.y);
-  const I cs[3] = {I(q.n[1] * q.n[2]), I(q.n[2]), 1};  // cell strides of phi
+  const int64_t n[3] = {q.n[0], q.n[1], q.n[2]};
+  const int64_t cs[3] = {n[1] * n[2], n[2], 1};  // cell strides of phi
   if (d == 3) {
     if (!add_p) return;
     D* p = static_cast<D*>(q.p);
-    const I total = I(q.n[0] * q.n[1] * q.n[2]);
-    for (I i = I(blockIdx.x) * PROJ_NT + threadIdx.x; i < total; i += I(gridDim.x) * PROJ_NT)
+    const int64_t total = n[0] * n[1] * n[2];
+    for (int64_t i = int64_t(blockIdx.x) * PROJ_NT + threadIdx.x; i < total; i += int64_t(gridDim.x) * PROJ_NT)
       p[i] = D(double(p[i]) + double(phi[i]));
     return;
   }
   if (!((mask >> d) & 1) || !q.vel[d]) return;
   D* u = static_cast<D*>(q.vel[d]);
-  const I n = I(q.n[d]);
   const int ext = q.ext[d];
-  I s[3] = {I(q.n[0]), I(q.n[1]), I(q.n[2])};
-  s[d] += I(ext);
-  const I total = s[0] * s[1] * s[2];
+  int64_t s[3] = {n[0], n[1], n[2]};
+  s[d] += ext;
   const double cu = q.adt * q.inv_h[d];
-  for (I i = I(blockIdx.x) * PROJ_NT + threadIdx.x; i < total; i += I(gridDim.x) * PROJ_NT) {
-    I c[3];
-    unflatten(i, s, c);
-    const I f = c[d];
-    c[d] = f < n ? f : n - 1;  // cell above the face (below it for face n)
-    const I o = c[0] * cs[0] + c[1] * cs[1] + c[2] * cs[2];
-    double g;
-    if (ext == 0) {
-      g = double(phi[o]) - double(phi[f == 0 ? o + (n - 1) * cs[d] : o - cs[d]]);
-    } else if (f == 0) {
-      if (!q.dlo[d]) continue;  // Neumann face: no flux, the velocity stays
-      g = 2.0 * double(phi[o]);
-    } else if (f == n) {
-      if (!q.dhi[d]) continue;
-      g = -2.0 * double(phi[o]);
-    } else {
-      g = double(phi[o]) - double(phi[o - cs[d]]);
+  for (int64_t row = blockIdx.x; row < s[0] * s[1]; row += gridDim.x) {
+    const int64_t c0 = row / s[1], c1 = row - c0 * s[1];
+    D* ur = u + row * s[2];
+    if (d == 2) {
+      // faces along the row: phi of the same row, cells f - 1 and f
+      const D* pr = phi + c0 * cs[0] + c1 * cs[1];
+      const int64_t nn = n[2];
+      for (int64_t f = threadIdx.x; f < s[2]; f += PROJ_NT) {
+        double g;
+        if (ext == 0) g = double(pr[f]) - double(pr[f == 0 ? nn - 1 : f - 1]);
+        else if (f == 0) { if (!q.dlo[2]) continue; g = 2.0 * double(pr[0]); }
+        else if (f == nn) { if (!q.dhi[2]) continue; g = -2.0 * double(pr[nn - 1]); }
+        else g = double(pr[f]) - double(pr[f - 1]);
+        ur[f] = D(double(ur[f]) - cu * g);
+      }
+      continue;
     }
-    u[i] = D(double(u[i]) - cu * g);
+    // faces across rows: the face index is c_d; phi rows of cells f and f - 1
+    const int64_t f = d == 0 ? c0 : c1;
+    const int64_t nd = n[d];
+    int64_t cc[2] = {c0, c1};
+    cc[d] = f < nd ? f : nd - 1;  // the cell above the face (below it for face n)
+    const D* hi = phi + cc[0] * cs[0] + cc[1] * cs[1];
+    const D* lo = nullptr;
+    double chi = 1.0, clo = -1.0;  // g = chi * phi[hi] + clo * phi[lo]
+    if (ext == 0) {
+      lo = f == 0 ? hi + (nd - 1) * cs[d] : hi - cs[d];
+    } else if (f == 0) {
+      if (!q.dlo[d]) continue;  // Neumann face: the velocity stays
+      chi = 2.0;
+    } else if (f == nd) {
+      if (!q.dhi[d]) continue;
+      chi = -2.0;
+    } else {
+      lo = hi - cs[d];
+    }
+    for (int64_t c2 = threadIdx.x; c2 < n[2]; c2 += PROJ_NT) {
+      const double g = chi * double(hi[c2]) + (lo ? clo * double(lo[c2]) : 0.0);
+      ur[c2] = D(double(ur[c2]) - cu * g);
+    }
   }
 }
 
-template <typename D>
-__global__ void __launch_bounds__(PROJ_NT) proj_correct_kernel(ProjDev q, const D* phi, int mask, int add_p,
-                                                               int wide) {
-  if (wide) correct<D, int64_t>(q, phi, mask, add_p);
-  else correct<D, uint32_t>(q, phi, mask, add_p);
-}
-
-// Largest element count among the velocity components and the cells.
-int64_t proj_extent(const ProjDev& q) {
-  int64_t m = q.n[0] * q.n[1] * q.n[2];
-  for (int d = 0; d < 3; ++d) {
-    int64_t s[3] = {q.n[0], q.n[1], q.n[2]};
-    s[d] += q.ext[d];
-    m = s[0] * s[1] * s[2] > m ? s[0] * s[1] * s[2] : m;
-  }
-  return m;
-}
-
-unsigned proj_blocks(int64_t count) {
-  const int64_t b = (count + PROJ_NT - 1) / PROJ_NT;
-  return unsigned(b < 4096 ? (b > 0 ? b : 1) : 4096);
+unsigned proj_blocks(int64_t rows) {
+  return unsigned(rows < 16384 ? (rows > 0 ? rows : 1) : 16384);
 }
 
 }  // namespace
 
 hipError_t launch_proj_div(const ProjDev& q, double* g, hipStream_t s) {
-  const int64_t ext = proj_extent(q);
-  hipLaunchKernelGGL(proj_div_kernel, dim3(proj_blocks(q.n[0] * q.n[1] * q.n[2])), dim3(PROJ_NT), 0, s, q, g,
-                     int(ext >= (int64_t(1) << 31)));
+  hipLaunchKernelGGL(proj_div_kernel, dim3(proj_blocks(q.n[0] * q.n[1])), dim3(PROJ_NT), 0, s, q, g);
   return hipGetLastError();
 }
 
 hipError_t launch_proj_correct(const ProjDev& q, const void* phi, int f64, int mask, int add_p, hipStream_t s) {
-  const int64_t ext = proj_extent(q);
-  const dim3 grid(proj_blocks(ext), 4);
-  const int wide = int(ext >= (int64_t(1) << 31));
+  // rows of the largest component (axis 0 or 1 may have one more face)
+  const int64_t rows = (q.n[0] + q.ext[0]) * (q.n[1] + q.ext[1]);
+  const dim3 grid(proj_blocks(rows), 4);
   if (f64)
     hipLaunchKernelGGL(proj_correct_kernel<double>, grid, dim3(PROJ_NT), 0, s, q, static_cast<const double*>(phi),
-                       mask, add_p, wide);
+                       mask, add_p);
   else
     hipLaunchKernelGGL(proj_correct_kernel<float>, grid, dim3(PROJ_NT), 0, s, q, static_cast<const float*>(phi), mask,
-                       add_p, wide);
+                       add_p);
   return hipGetLastError();
 }
 
