@@ -1204,17 +1204,32 @@ __device__ __forceinline__ void idx_divmod(int64_t x, int64_t d, int64_t* q, int
 // line l is div(vel) / adt at cell (l / n1, l % n1, j), summed in FP64 over
 // the velocity components present.  Lanes take consecutive j of one line, so
 // the three component reads are coalesced.
+// Cell coordinates (c0, c1) of line l0 + t, from those of the tile's first
+// line (lines run over axis 1 fastest; a division only where t wraps it).
+__device__ __forceinline__ void line_cell(int64_t c0_0, int64_t c1_0, int t, int64_t n1, int64_t* c0, int64_t* c1) {
+  int64_t a1 = c1_0 + t, a0 = c0_0;
+  if (a1 >= n1) {
+    const int64_t k = a1 / n1;
+    a0 += k;
+    a1 -= k * n1;
+  }
+  *c0 = a0;
+  *c1 = a1;
+}
+
 template <typename T, typename S, int TL, int NT, int XP>
 __device__ __forceinline__ void proj_div_load(T* X, const PassArgs& a, int64_t l0, int n) {
   const ProjDev& q = a.proj;
   const int total = TL * n;
+  int64_t c0_0, c1_0;
+  idx_divmod(l0, q.n[1], &c0_0, &c1_0);
   for (int e = int(threadIdx.x); e < total; e += NT) {
     const int t = e / n, j = e - t * n;
     const int64_t l = l0 + t;
     double sum = 0.0;
     if (l < a.nlines) {
       int64_t c[3];
-      idx_divmod(l, q.n[1], &c[0], &c[1]);
+      line_cell(c0_0, c1_0, t, q.n[1], &c[0], &c[1]);
       c[2] = j;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -1244,6 +1259,8 @@ __device__ __forceinline__ void proj_store(const T* X, const PassArgs& a, int64_
   const int nf = n + q.ext[2];
   const double cw = q.adt * q.inv_h[2];
   const int total = TL * nf;
+  int64_t c0_0, c1_0;
+  idx_divmod(l0, q.n[1], &c0_0, &c1_0);
   for (int e = int(threadIdx.x); e < total; e += NT) {
     const int t = e / nf, f = e - t * nf;
     const int64_t l = l0 + t;
@@ -1270,7 +1287,7 @@ __device__ __forceinline__ void proj_store(const T* X, const PassArgs& a, int64_
       }
       if (upd) {
         int64_t c0, c1;
-        idx_divmod(l, q.n[1], &c0, &c1);
+        line_cell(c0_0, c1_0, t, q.n[1], &c0, &c1);
         const int64_t ow = c0 * q.vs[2][0] + c1 * q.vs[2][1] + f;
         w[ow] = D(double(w[ow]) - cw * g);
       }
