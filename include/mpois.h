@@ -20,6 +20,18 @@
  *    and the host is not synchronised by mpois_execute / mpois_execute_batch.
  *  - A plan may be used by one stream at a time; distinct plans are
  *    independent.
+ *
+ * Environment variables read by the library
+ *  - MPOIS_TUNE_CACHE=<file>: the autotuner's decisions are read from and
+ *    appended to this file (keyed by gfx arch, CU count, HIP version and the
+ *    library's build hash).
+ *  - MPOIS_LOG=1: the autotuner prints every candidate's time and its choice.
+ *  - MPOIS_TRACE=1: roctx ranges around the library's calls and the phases of
+ *    a solve (solve, residual, batch solve, batch residual), for
+ *    rocprofv3 --marker-trace.
+ *  - Test hooks: MPOIS_NO_SPEC=1 (no kernels compiled for one transform),
+ *    MPOIS_NO_PLANE=1 (no plane kernels), MPOIS_TUNE_VARIANT=k (the tuner
+ *    times only radix plan k), MPOIS_FAULT_ALLOC=1 (device allocations fail).
  */
 #ifndef MPOIS_H
 #define MPOIS_H
