@@ -22,12 +22,14 @@ constexpr int MAX_STAGES = 16;
 
 // One Stockham stage: radix, product of the radices before it (ns), offset of
 // its twiddles e^{-2 pi i r k/(ns R)} (k < ns, 1 <= r < R) and, for odd radices
-// of 5 and above, of the R constants e^{2 pi i j/R} used by the codelet.
+// of 5 and above, of the R constants e^{2 pi i j/R} used by the codelet; and a
+// reciprocal of ns for the quotients of the run-time stage loop.
 struct Stage {
   int radix;
   int ns;
   int tw_off;
   int cs_off;
+  unsigned ns_mul;  // floor(2^32 / ns) + 1 (0 when ns = 1): b mod ns without a division (b < 2^16)
 };
 
 // Device description of the complex DFT that one axis's line transforms use.

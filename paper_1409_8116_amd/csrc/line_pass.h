@@ -363,13 +363,27 @@ __device__ __forceinline__ void dft_any(cx<T>* v) {
 // it, so the stage runs in place in one buffer.
 // PC, NSC: compile-time work length and stage stride (0: the run-time P, ns).
 template <typename T, int R, int NP, int NT, int PMAX, int PC = 0, int NSC = 0, int ZP = NP>
-__device__ __forceinline__ void stage(cx<T>* Z, int P_rt, int ns_rt, const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void stage(cx<T>* Z, int P_rt, int ns_rt, const cx<T>* __restrict__ tw,
+                                      unsigned ns_mul = 0) {
   constexpr int NB = (((PC ? PC : PMAX) / R) * NP + NT - 1) / NT;
   const int P = PC ? PC : P_rt;
   const int ns = NSC ? NSC : ns_rt;
   const int nbp = P / R;      // butterflies per pair
   const int items = nbp * NP;
   const int tid = opaque_tid();
+  // b mod ns: a constant, or (FP32 run-time stage lists; b < 2^16) a
+  // multiply by the stage's scaled reciprocal.  The FP64 shapes held to 128
+  // registers keep the division: the reciprocal's registers made them spill.
+  auto mod_ns = [&](int b) -> int {
+    if constexpr (NSC != 0) {
+      return b % NSC;
+    } else if constexpr (sizeof(T) == 4) {
+      if (ns_mul) return b - int(__umulhi(unsigned(b), ns_mul)) * ns;
+      return 0;  // ns == 1
+    } else {
+      return b % ns;
+    }
+  };
   cx<T> v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -380,7 +394,7 @@ __device__ __forceinline__ void stage(cx<T>* Z, int P_rt, int ns_rt, const cx<T>
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = Z[(b + r * nbp) * ZP + p];
       if (ns > 1) {
-        const int k = b % ns;
+        const int k = mod_ns(b);
         const cx<T>* w = tw + k * (R - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[r - 1]);
@@ -396,7 +410,7 @@ __device__ __forceinline__ void stage(cx<T>* Z, int P_rt, int ns_rt, const cx<T>
     if (item < items) {
       const int p = item % NP;
       const int b = item / NP;
-      const int k = b % ns;
+      const int k = mod_ns(b);
       const int base = (b - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) Z[(base + r * ns) * ZP + p] = v[i][r];
@@ -690,44 +704,44 @@ __device__ __forceinline__ void dft_engine(cx<T>* Z, int P, int nstages, const S
     const Stage st = stp[s];
     const cx<T>* t = tw + st.tw_off;
     switch (st.radix) {
-      case 2: stage<T, 2, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 3: stage<T, 3, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 4: stage<T, 4, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 5: stage<T, 5, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 7: stage<T, 7, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 8: stage<T, 8, NP, NT, PMAX>(Z, P, st.ns, t); break;
-      case 9: stage<T, 9, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 2: stage<T, 2, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul); break;
+      case 3: stage<T, 3, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul); break;
+      case 4: stage<T, 4, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul); break;
+      case 5: stage<T, 5, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul); break;
+      case 7: stage<T, 7, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul); break;
+      case 8: stage<T, 8, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul); break;
+      case 9: stage<T, 9, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul); break;
       case 11:
-        if constexpr (SLIM != 1) stage<T, 11, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (SLIM != 1) stage<T, 11, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul);
         break;
       case 13:
-        if constexpr (SLIM != 1) stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (SLIM != 1) stage<T, 13, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul);
         break;
       // primes 17..31: only in the wide shapes (SLIM == 2)
       case 17:
-        if constexpr (SLIM == 2) stage<T, 17, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (SLIM == 2) stage<T, 17, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul);
         break;
       case 19:
-        if constexpr (SLIM == 2) stage<T, 19, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (SLIM == 2) stage<T, 19, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul);
         break;
       case 23:
-        if constexpr (SLIM == 2) stage<T, 23, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (SLIM == 2) stage<T, 23, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul);
         break;
       case 29:
-        if constexpr (SLIM == 2) stage<T, 29, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (SLIM == 2) stage<T, 29, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul);
         break;
       case 31:
-        if constexpr (SLIM == 2) stage<T, 31, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (SLIM == 2) stage<T, 31, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul);
         break;
       case 14:
         // only after a Rader stage (1022 = 73 x 14): one LDS sweep instead of 7 and 2
-        if constexpr (RADER != 0) stage<T, 14, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (RADER != 0) stage<T, 14, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul);
         break;
-      case 16: stage<T, 16, NP, NT, PMAX>(Z, P, st.ns, t); break;
+      case 16: stage<T, 16, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul); break;
       case 32:
         // largest power-of-two codelet: 32 in FP32 only (keeps FP64 threads
         // near 100 registers, so two workgroups share a CU)
-        if constexpr (sizeof(T) == 4) stage<T, 32, NP, NT, PMAX>(Z, P, st.ns, t);
+        if constexpr (sizeof(T) == 4) stage<T, 32, NP, NT, PMAX>(Z, P, st.ns, t, st.ns_mul);
         break;
       case 73:
         if constexpr (RADER != 0) stage_rader73<T, NP, NT, PMAX, RADER>(Z, P, st.ns, t, cs + st.cs_off);

@@ -543,6 +543,9 @@ mpois_status build_axis_tables(mpois_plan_s* pl, AxisTables* at) {
     Stage& st = stages[i];
     st.radix = R;
     st.ns = int(ns);
+    // q = umulhi(b, ns_mul) equals b / ns for b < 2^16 and ns < 2^16 (the
+    // error b 2^-32 of the scaled reciprocal stays below 1/ns)
+    st.ns_mul = ns > 1 ? unsigned((uint64_t(1) << 32) / uint64_t(ns) + 1) : 0u;
     st.tw_off = int(tw.size());
     for (int64_t k = 0; k < ns; ++k)
       for (int r = 1; r < R; ++r) {
