@@ -8,7 +8,7 @@
 
 #define MPOIS_PLANES(X)                              \
   /* 32 x 32 periodic planes (FP64: 8 x 4 stages, FP32: one radix-32 stage) */ \
-  X(0, double, 256, 32, 32, 32, 0, 1, 8, 4)          \
-  X(1, float, 256, 32, 32, 32, 0, 1, 32)
+  X(0, double, 1024, 32, 32, 32, 0, 1, 8, 4)          \
+  X(1, float, 1024, 32, 32, 32, 0, 1, 32)
 
 #define MPOIS_NUM_PLANES 2
