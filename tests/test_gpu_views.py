@@ -37,6 +37,7 @@ CASES = [
     ((512, 6, 512), (1, 1, 2), ("N", "N", "N"), ("v", "v", "v")),   # specialised DCT-I kernels, generic tile path
     ((45, 64), (3, 2), ("D", "N"), ("v", "s")),
     ((300,), (5,), (("N", "D"),), ("s",)),
+    ((6, 32, 32), (1, 2, 1), ("P", "P", "P"), ("v", "v", "v")),  # plane-kernel shape: views use the per-axis sweeps
 ]
 
 

@@ -58,6 +58,13 @@ def test_noalloc_matches_execute_twice_second_smaller(prec):
     _run(mp, (17, 12, 9), ("N", "N", "P"), ("s", "v", "v"), prec, seed=2)
 
 
+@pytest.mark.parametrize("prec", ["f32r", "f64"])
+def test_noalloc_with_plane_kernels(prec):
+    """32 x 32 periodic planes (the plane-kernel path) through the static scratch."""
+    import paper_1409_8116_amd as mp
+    _run(mp, (12, 32, 32), ("P", "P", "P"), ("v", "v", "v"), prec, seed=4)
+
+
 def test_noalloc_full_scratch_size_and_refusal():
     import paper_1409_8116_amd as mp
     _run(mp, (256, 256, 256), ("N", "N", "N"), ("v", "v", "v"), "f32r", seed=3)  # 64 MiB working array
