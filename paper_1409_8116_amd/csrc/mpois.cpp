@@ -400,6 +400,12 @@ struct BatchState {
   void** staging = nullptr;
   hipEvent_t uploaded = nullptr;
   bool have_tables = false;
+  // The kernel-shape groups of one sweep touch disjoint grids: they run on
+  // the execute's stream and side streams (forked and joined by events), so
+  // a small group fills the chip while a large one drains.
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
 };
 
 struct Graph {
@@ -1031,6 +1037,9 @@ void free_plan(mpois_plan_s* pl) {
   }
   if (pl->batch.staging) (void)hipHostFree(pl->batch.staging);
   if (pl->batch.uploaded) (void)hipEventDestroy(pl->batch.uploaded);
+  for (hipStream_t t : pl->batch.side) (void)hipStreamDestroy(t);
+  if (pl->batch.fork) (void)hipEventDestroy(pl->batch.fork);
+  for (hipEvent_t e : pl->batch.join) (void)hipEventDestroy(e);
   for (DevBuf* b : {&pl->batch.rhs_tab, &pl->batch.phi_tab, &pl->batch.work_tab, &pl->batch.resid_args,
                     &pl->batch.blk_prob, &pl->batch.blk_start, &pl->batch.blk_count, &pl->batch.inv_wsum,
                     &pl->batch.partials})
@@ -1338,6 +1347,19 @@ mpois_status build_batch(mpois_plan_s* pl) {
     return MPOIS_ERR_NOMEM;
   }
   if (hipEventCreateWithFlags(&B.uploaded, hipEventDisableTiming) != hipSuccess) return MPOIS_ERR_DEVICE;
+  size_t max_groups = 0;
+  for (const BatchPass& bp : B.passes) max_groups = std::max(max_groups, bp.groups.size());
+  constexpr size_t kSide = 3;
+  const size_t nside = std::min(kSide, max_groups > 0 ? max_groups - 1 : 0);
+  if (nside > 0 && hipEventCreateWithFlags(&B.fork, hipEventDisableTiming) != hipSuccess) return MPOIS_ERR_DEVICE;
+  for (size_t i = 0; i < nside; ++i) {
+    hipStream_t t = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess) return MPOIS_ERR_DEVICE;
+    B.side.push_back(t);
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return MPOIS_ERR_DEVICE;
+    B.join.push_back(e);
+  }
   if (pl->prec == MPOIS_F32_REFINE) {
     std::vector<void*> work(static_cast<size_t>(count));
     int64_t off = 0;
@@ -1368,11 +1390,24 @@ hipError_t batch_solve(mpois_plan_s* pl, const void* const* in, int in_f64, void
     b.update = (last && update) ? 1 : 0;
     b.shift_base = static_cast<const double*>(pl->scalars.p) + S_SHIFT;
     b.shift_stride = S_COUNT;
-    for (const BatchGroup& g : B.passes[p].groups) {
+    const auto& groups = B.passes[p].groups;
+    const size_t nside = std::min(B.side.size(), groups.size() > 0 ? groups.size() - 1 : 0);
+    hipError_t e = hipSuccess;
+    if (nside > 0) {
+      if ((e = hipEventRecord(B.fork, s)) != hipSuccess) return e;
+      for (size_t k = 0; k < nside; ++k)
+        if ((e = hipStreamWaitEvent(B.side[k], B.fork, 0)) != hipSuccess) return e;
+    }
+    for (size_t i = 0; i < groups.size(); ++i) {
+      const BatchGroup& g = groups[i];
       b.tile_prob = static_cast<const int*>(g.tile_prob.p);
       b.tile_idx = static_cast<const int*>(g.tile_idx.p);
-      hipError_t e = launch_line_pass_batch(g.cfg, b, g.blocks, g.lds, s);
-      if (e != hipSuccess) return e;
+      hipStream_t t = (i == 0 || nside == 0) ? s : B.side[(i - 1) % nside];
+      if ((e = launch_line_pass_batch(g.cfg, b, g.blocks, g.lds, t)) != hipSuccess) return e;
+    }
+    for (size_t k = 0; k < nside; ++k) {
+      if ((e = hipEventRecord(B.join[k], B.side[k])) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(s, B.join[k], 0)) != hipSuccess) return e;
     }
   }
   return hipSuccess;
