@@ -152,3 +152,15 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 def test_project_null_arguments(mp):
     lib = mp.load_library()
     assert lib.mpois_project(None, None, None, 0.5, None, None) == 1
+
+
+def test_longest_axes_validate(mp):
+    """Work length 8192 is the longest line a kernel shape holds: the axes
+    that reach it validate, one point more (or a prime whose Bluestein
+    length exceeds it) is UNSUPPORTED, in every precision."""
+    for bc, grid, n, want in [("P", "v", 8192, 0), ("N", "v", 4097, 0), ("D", "v", 4095, 0), ("N", "s", 8192, 0),
+                              ("D", "s", 8192, 0), ("P", "v", 4093, 0), ("P", "v", 8191, 2), ("P", "v", 16384, 2),
+                              ("N", "s", 8193, 2), ("N", "v", 4098, 2)]:
+        for prec in ("f64", "f32", "f32r"):
+            assert mp.validate((n,), (1.0 / n,), (bc,), (grid,), prec=prec) == want, (bc, grid, n, prec)
+        assert mp.validate((n, 4), (1.0 / n, 0.2), (bc, "D"), (grid, "v")) == want, (bc, grid, n)

@@ -416,3 +416,18 @@ def test_mixed_face_closures_by_hand():
     assert np.array_equal(nd_s, np.array([[-1, 1, 0], [1, -2, 1], [0, 1, -3]], dtype=float))
     # one unknown: vertex D|N closes with the Dirichlet node (0) on both sides of the mirror
     assert np.array_equal(oracle.assemble_1d("DN", "v", 1, 1.0), np.array([[-2.0]]))
+
+
+def test_eigenmode_helper_matches_assembled_stencil():
+    """The closed-form eigenpairs the longest-line GPU tests use are exact
+    eigenpairs of the oracle's assembled 1D stencil, for every kind."""
+    from eigenmodes import eigenpair
+    from oracle.fd import assemble_1d
+    for bc, grid in [("P", "v"), ("N", "v"), ("D", "v"), ("N", "s"), ("D", "s")]:
+        for n in (5, 8, 9, 16):
+            h = 0.37
+            L = assemble_1d(bc, grid, n, h)
+            for k in range(n):
+                v, lam = eigenpair(bc, grid, n, k, h)
+                assert np.linalg.norm(L @ v - lam * v) <= 1e-12 * max(abs(lam), 1.0) * np.linalg.norm(v), \
+                    (bc, grid, n, k)
