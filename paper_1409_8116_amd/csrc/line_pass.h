@@ -1217,7 +1217,8 @@ __device__ __forceinline__ void idx_divmod(int64_t x, int64_t d, int64_t* q, int
 // First pass of a projection step (along the last padded axis): element j of
 // line l is div(vel) / adt at cell (l / n1, l % n1, j), summed in FP64 over
 // the velocity components present.  Lanes take consecutive j of one line, so
-// the three component reads are coalesced.
+// the three component reads are coalesced; each thread issues the face reads
+// of PDU elements before it uses any of them (more requests in flight).
 // Cell coordinates (c0, c1) of line l0 + t, from those of the tile's first
 // line (lines run over axis 1 fastest; a division only where t wraps it).
 __device__ __forceinline__ void line_cell(int64_t c0_0, int64_t c1_0, int t, int64_t n1, int64_t* c0, int64_t* c1) {
@@ -1233,30 +1234,50 @@ __device__ __forceinline__ void line_cell(int64_t c0_0, int64_t c1_0, int t, int
 
 template <typename T, typename S, int TL, int NT, int XP>
 __device__ __forceinline__ void proj_div_load(T* X, const PassArgs& a, int64_t l0, int n) {
+  constexpr int PDU = 4;
   const ProjDev& q = a.proj;
   const int total = TL * n;
   int64_t c0_0, c1_0;
   idx_divmod(l0, q.n[1], &c0_0, &c1_0);
-  for (int e = int(threadIdx.x); e < total; e += NT) {
-    const int t = e / n, j = e - t * n;
-    const int64_t l = l0 + t;
-    double sum = 0.0;
-    if (l < a.nlines) {
+  for (int e0 = int(threadIdx.x); e0 < total; e0 += PDU * NT) {
+    // faces below and above each of the PDU cells, per component (zeros for
+    // absent components and for elements past the tile or the last line)
+    S lo[PDU][3], hi[PDU][3];
+#pragma unroll
+    for (int i = 0; i < PDU; ++i) {
+      const int e = e0 + i * NT;
+      const int t = e / n, j = e - t * n;
+      const bool ok = e < total && l0 + t < a.nlines;
       int64_t c[3];
-      line_cell(c0_0, c1_0, t, q.n[1], &c[0], &c[1]);
-      c[2] = j;
+      line_cell(c0_0, c1_0, ok ? t : 0, q.n[1], &c[0], &c[1]);
+      c[2] = ok ? j : 0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const S* u = static_cast<const S*>(q.vel[d]);
-        if (!u) continue;
+        lo[i][d] = S(0);
+        hi[i][d] = S(0);
+        if (!u || !ok) continue;
         const int64_t o = c[0] * q.vs[d][0] + c[1] * q.vs[d][1] + c[2] * q.vs[d][2];
         // the face above cell c; on a periodic axis face n is face 0
         const int64_t up = (q.ext[d] == 0 && c[d] + 1 == q.n[d]) ? o - (q.n[d] - 1) * q.vs[d][d] : o + q.vs[d][d];
-        sum += (double(u[up]) - double(u[o])) * q.inv_h[d];
+        lo[i][d] = u[o];
+        hi[i][d] = u[up];
       }
-      sum *= q.inv_adt;
     }
-    X[j * XP + t] = T(sum);
+#pragma unroll
+    for (int i = 0; i < PDU; ++i) {
+      const int e = e0 + i * NT;
+      if (e >= total) break;
+      const int t = e / n, j = e - t * n;
+      double sum = 0.0;
+      if (l0 + t < a.nlines) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (q.vel[d]) sum += (double(hi[i][d]) - double(lo[i][d])) * q.inv_h[d];
+        sum *= q.inv_adt;
+      }
+      X[j * XP + t] = T(sum);
+    }
   }
 }
 
@@ -1275,35 +1296,50 @@ __device__ __forceinline__ void proj_store(const T* X, const PassArgs& a, int64_
   const int total = TL * nf;
   int64_t c0_0, c1_0;
   idx_divmod(l0, q.n[1], &c0_0, &c1_0);
-  for (int e = int(threadIdx.x); e < total; e += NT) {
-    const int t = e / nf, f = e - t * nf;
-    const int64_t l = l0 + t;
-    if (l >= a.nlines) continue;
-    if (f < n) {
-      const double x = double(X[f * XP + t]);
-      const int64_t o = l * int64_t(n) + f;
-      phi[o] = D(x);
-      p[o] = D(double(p[o]) + x);
-    }
-    if (w) {
-      double g;
-      bool upd = true;
-      if (q.ext[2] == 0) {
-        g = double(X[f * XP + t]) - double(X[(f == 0 ? n - 1 : f - 1) * XP + t]);
-      } else if (f == 0) {
-        upd = q.dlo[2] != 0;
-        g = 2.0 * double(X[t]);
-      } else if (f == n) {
-        upd = q.dhi[2] != 0;
-        g = -2.0 * double(X[(n - 1) * XP + t]);
-      } else {
-        g = double(X[f * XP + t]) - double(X[(f - 1) * XP + t]);
-      }
-      if (upd) {
+  // PSU elements per thread at a time: the reads of p and of the faces of w
+  // for all of them are issued before any of them is updated
+  constexpr int PSU = 4;
+  for (int e0 = int(threadIdx.x); e0 < total; e0 += PSU * NT) {
+    D pv[PSU], wv[PSU];
+    int64_t ow[PSU];
+#pragma unroll
+    for (int i = 0; i < PSU; ++i) {
+      const int e = e0 + i * NT;
+      const int t = e / nf, f = e - t * nf;
+      const bool ok = e < total && l0 + t < a.nlines;
+      pv[i] = D(0);
+      wv[i] = D(0);
+      ow[i] = -1;
+      if (!ok) continue;
+      if (f < n) pv[i] = p[(l0 + t) * int64_t(n) + f];
+      // a Dirichlet boundary face is corrected, a Neumann one keeps its value
+      const bool upd = q.ext[2] == 0 || (f == 0 ? q.dlo[2] != 0 : f == n ? q.dhi[2] != 0 : true);
+      if (w && upd) {
         int64_t c0, c1;
         line_cell(c0_0, c1_0, t, q.n[1], &c0, &c1);
-        const int64_t ow = c0 * q.vs[2][0] + c1 * q.vs[2][1] + f;
-        w[ow] = D(double(w[ow]) - cw * g);
+        ow[i] = c0 * q.vs[2][0] + c1 * q.vs[2][1] + f;
+        wv[i] = w[ow[i]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PSU; ++i) {
+      const int e = e0 + i * NT;
+      if (e >= total) break;
+      const int t = e / nf, f = e - t * nf;
+      if (l0 + t >= a.nlines) continue;
+      if (f < n) {
+        const double x = double(X[f * XP + t]);
+        const int64_t o = (l0 + t) * int64_t(n) + f;
+        phi[o] = D(x);
+        p[o] = D(double(pv[i]) + x);
+      }
+      if (ow[i] >= 0) {
+        double g;
+        if (q.ext[2] == 0) g = double(X[f * XP + t]) - double(X[(f == 0 ? n - 1 : f - 1) * XP + t]);
+        else if (f == 0) g = 2.0 * double(X[t]);
+        else if (f == n) g = -2.0 * double(X[(n - 1) * XP + t]);
+        else g = double(X[f * XP + t]) - double(X[(f - 1) * XP + t]);
+        w[ow[i]] = D(double(wv[i]) - cw * g);
       }
     }
   }
