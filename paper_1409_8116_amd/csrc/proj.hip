@@ -56,62 +56,6 @@ __global__ void __launch_bounds__(PROJ_NT) proj_div_kernel(ProjDev q, double* g)
   }
 }
 
-// Faces of component d < 2 in row `row` of its face array (shape s): the
-// face index is c_d, and g = chi phi[hi] + clo phi[lo] from the phi rows of
-// the cells above and below the face (a Dirichlet boundary face has only
-// the cell inside, doubled; a Neumann one keeps its velocity: act false).
-struct FaceRow {
-  int64_t hi, lo;  // phi row offsets (lo < 0: none)
-  double chi, clo;
-  bool act;
-};
-
-__device__ __forceinline__ FaceRow face_row(const ProjDev& q, int d, int64_t row, const int64_t s[3],
-                                            const int64_t cs[3]) {
-  const int64_t c0 = row / s[1], c1 = row - c0 * s[1];
-  const int64_t f = d == 0 ? c0 : c1;
-  const int64_t nd = q.n[d];
-  int64_t cc[2] = {c0, c1};
-  cc[d] = f < nd ? f : nd - 1;  // the cell above the face (below it for face n)
-  FaceRow r{cc[0] * cs[0] + cc[1] * cs[1], -1, 1.0, -1.0, true};
-  if (q.ext[d] == 0) {
-    r.lo = f == 0 ? r.hi + (nd - 1) * cs[d] : r.hi - cs[d];
-  } else if (f == 0) {
-    r.act = q.dlo[d] != 0;
-    r.chi = 2.0;
-  } else if (f == nd) {
-    r.act = q.dhi[d] != 0;
-    r.chi = -2.0;
-  } else {
-    r.lo = r.hi - cs[d];
-  }
-  return r;
-}
-
-// u_d -= adt grad_d phi for d < 2, two rows per step per block: the reads of
-// both rows are issued before either is written (more requests in flight).
-template <typename D>
-__device__ __forceinline__ void correct_across_rows(const ProjDev& q, const D* __restrict__ phi, D* __restrict__ u,
-                                                    int d, const int64_t s[3], const int64_t cs[3], double cu) {
-  const int64_t rows = s[0] * s[1];
-  const int64_t G = gridDim.x;
-  for (int64_t row = blockIdx.x; row < rows; row += 2 * G) {
-    const int64_t rowb = row + G;
-    const FaceRow a = face_row(q, d, row, s, cs);
-    const FaceRow b = rowb < rows ? face_row(q, d, rowb, s, cs) : FaceRow{0, -1, 0.0, 0.0, false};
-    for (int64_t c2 = threadIdx.x; c2 < s[2]; c2 += PROJ_NT) {
-      const double ha = a.act ? double(phi[a.hi + c2]) : 0.0;
-      const double la = a.act && a.lo >= 0 ? double(phi[a.lo + c2]) : 0.0;
-      const double ua = a.act ? double(u[row * s[2] + c2]) : 0.0;
-      const double hb = b.act ? double(phi[b.hi + c2]) : 0.0;
-      const double lb = b.act && b.lo >= 0 ? double(phi[b.lo + c2]) : 0.0;
-      const double ub = b.act ? double(u[rowb * s[2] + c2]) : 0.0;
-      if (a.act) u[row * s[2] + c2] = D(ua - cu * (a.chi * ha + (a.lo >= 0 ? a.clo * la : 0.0)));
-      if (b.act) u[rowb * s[2] + c2] = D(ub - cu * (b.chi * hb + (b.lo >= 0 ? b.clo * lb : 0.0)));
-    }
-  }
-}
-
 // Component d (blockIdx.y < 3, when bit d of mask is set): u_d -= adt grad_d phi
 // on every face; blockIdx.y == 3 (when add_p): p += phi.
 template <typename D>
@@ -133,23 +77,45 @@ __global__ void __launch_bounds__(PROJ_NT) proj_correct_kernel(ProjDev q, const 
   int64_t s[3] = {n[0], n[1], n[2]};
   s[d] += ext;
   const double cu = q.adt * q.inv_h[d];
-  if (d < 2) {
-    correct_across_rows(q, phi, u, d, s, cs, cu);
-    return;
-  }
   for (int64_t row = blockIdx.x; row < s[0] * s[1]; row += gridDim.x) {
     const int64_t c0 = row / s[1], c1 = row - c0 * s[1];
     D* ur = u + row * s[2];
-    // faces along the row: phi of the same row, cells f - 1 and f
-    const D* pr = phi + c0 * cs[0] + c1 * cs[1];
-    const int64_t nn = n[2];
-    for (int64_t f = threadIdx.x; f < s[2]; f += PROJ_NT) {
-      double g;
-      if (ext == 0) g = double(pr[f]) - double(pr[f == 0 ? nn - 1 : f - 1]);
-      else if (f == 0) { if (!q.dlo[2]) continue; g = 2.0 * double(pr[0]); }
-      else if (f == nn) { if (!q.dhi[2]) continue; g = -2.0 * double(pr[nn - 1]); }
-      else g = double(pr[f]) - double(pr[f - 1]);
-      ur[f] = D(double(ur[f]) - cu * g);
+    if (d == 2) {
+      // faces along the row: phi of the same row, cells f - 1 and f
+      const D* pr = phi + c0 * cs[0] + c1 * cs[1];
+      const int64_t nn = n[2];
+      for (int64_t f = threadIdx.x; f < s[2]; f += PROJ_NT) {
+        double g;
+        if (ext == 0) g = double(pr[f]) - double(pr[f == 0 ? nn - 1 : f - 1]);
+        else if (f == 0) { if (!q.dlo[2]) continue; g = 2.0 * double(pr[0]); }
+        else if (f == nn) { if (!q.dhi[2]) continue; g = -2.0 * double(pr[nn - 1]); }
+        else g = double(pr[f]) - double(pr[f - 1]);
+        ur[f] = D(double(ur[f]) - cu * g);
+      }
+      continue;
+    }
+    // faces across rows: the face index is c_d; phi rows of cells f and f - 1
+    const int64_t f = d == 0 ? c0 : c1;
+    const int64_t nd = n[d];
+    int64_t cc[2] = {c0, c1};
+    cc[d] = f < nd ? f : nd - 1;  // the cell above the face (below it for face n)
+    const D* hi = phi + cc[0] * cs[0] + cc[1] * cs[1];
+    const D* lo = nullptr;
+    double chi = 1.0, clo = -1.0;  // g = chi * phi[hi] + clo * phi[lo]
+    if (ext == 0) {
+      lo = f == 0 ? hi + (nd - 1) * cs[d] : hi - cs[d];
+    } else if (f == 0) {
+      if (!q.dlo[d]) continue;  // Neumann face: the velocity stays
+      chi = 2.0;
+    } else if (f == nd) {
+      if (!q.dhi[d]) continue;
+      chi = -2.0;
+    } else {
+      lo = hi - cs[d];
+    }
+    for (int64_t c2 = threadIdx.x; c2 < n[2]; c2 += PROJ_NT) {
+      const double g = chi * double(hi[c2]) + (lo ? clo * double(lo[c2]) : 0.0);
+      ur[c2] = D(double(ur[c2]) - cu * g);
     }
   }
 }
