@@ -201,7 +201,14 @@ mpois_status mpois_project(mpois_plan plan, void* const* vel, void* p, double ad
 mpois_status mpois_execute_noalloc(mpois_plan plan, const void* rhs, void* phi, void* stream);
 
 /* Solve every grid of a batch plan: rhs[i], phi[i] are the device arrays of
- * grid i (host arrays of `count` device pointers). */
+ * grid i (host arrays of `count` device pointers).  The work is ordered on
+ * `stream`: within a sweep, the launches of different kernel shapes may run
+ * on up to three streams the plan owns, forked from `stream` and joined back
+ * to it by events, so work enqueued on `stream` afterwards sees the results
+ * (and a capture of `stream` records them as parallel branches).  The
+ * pointer arrays are validated and uploaded only when they change between
+ * calls; with MPOIS_FLAG_GRAPH the whole sequence is captured once and
+ * replayed. */
 mpois_status mpois_execute_batch(mpois_plan plan, const void* const* rhs, void* const* phi, void* stream);
 
 /* Residual report of the last execute (single-grid plans; for batch plans the
