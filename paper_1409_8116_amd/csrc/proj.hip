@@ -56,8 +56,45 @@ __global__ void __launch_bounds__(PROJ_NT) proj_div_kernel(ProjDev q, double* g)
   }
 }
 
+// Row (c0, c1) of the face array of component d < 2 (faces across rows: the
+// face index is c_d; phi rows of cells f and f - 1): u_d -= adt grad_d phi.
+template <typename D>
+__device__ __forceinline__ void correct_row_across(const ProjDev& q, const D* phi, int d, int64_t c0, int64_t c1) {
+  const int64_t n[3] = {q.n[0], q.n[1], q.n[2]};
+  const int64_t cs[3] = {n[1] * n[2], n[2], 1};  // cell strides of phi
+  const int ext = q.ext[d];
+  const int64_t s1 = n[1] + (d == 1 ? ext : 0);  // rows of the face array along axis 1
+  D* ur = static_cast<D*>(q.vel[d]) + (c0 * s1 + c1) * n[2];
+  const double cu = q.adt * q.inv_h[d];
+  const int64_t f = d == 0 ? c0 : c1;
+  const int64_t nd = n[d];
+  int64_t cc[2] = {c0, c1};
+  cc[d] = f < nd ? f : nd - 1;  // the cell above the face (below it for face n)
+  const D* hi = phi + cc[0] * cs[0] + cc[1] * cs[1];
+  const D* lo = nullptr;
+  double chi = 1.0, clo = -1.0;  // g = chi * phi[hi] + clo * phi[lo]
+  if (ext == 0) {
+    lo = f == 0 ? hi + (nd - 1) * cs[d] : hi - cs[d];
+  } else if (f == 0) {
+    if (!q.dlo[d]) return;  // Neumann face: the velocity stays
+    chi = 2.0;
+  } else if (f == nd) {
+    if (!q.dhi[d]) return;
+    chi = -2.0;
+  } else {
+    lo = hi - cs[d];
+  }
+  for (int64_t c2 = threadIdx.x; c2 < n[2]; c2 += PROJ_NT) {
+    const double g = chi * double(hi[c2]) + (lo ? clo * double(lo[c2]) : 0.0);
+    ur[c2] = D(double(ur[c2]) - cu * g);
+  }
+}
+
 // Component d (blockIdx.y < 3, when bit d of mask is set): u_d -= adt grad_d phi
-// on every face; blockIdx.y == 3 (when add_p): p += phi.
+// on every face; blockIdx.y == 3 (when add_p): p += phi.  When components 0
+// and 1 are both corrected, the blocks of y = 0 take both over the union of
+// their face rows (the phi row of the cell above a face is then read once
+// for the two) and those of y = 1 stay idle.
 template <typename D>
 __global__ void __launch_bounds__(PROJ_NT) proj_correct_kernel(ProjDev q, const D* phi, int mask, int add_p) {
   const int d = int(blockIdx.y);
@@ -72,6 +109,17 @@ __global__ void __launch_bounds__(PROJ_NT) proj_correct_kernel(ProjDev q, const 
     return;
   }
   if (!((mask >> d) & 1) || !q.vel[d]) return;
+  const bool both = (mask & 3) == 3 && q.vel[0] && q.vel[1];
+  if (both && d < 2) {
+    if (d == 1) return;
+    const int64_t r0 = n[0] + q.ext[0], r1 = n[1] + q.ext[1];
+    for (int64_t row = blockIdx.x; row < r0 * r1; row += gridDim.x) {
+      const int64_t c0 = row / r1, c1 = row - c0 * r1;
+      if (c1 < n[1]) correct_row_across(q, phi, 0, c0, c1);
+      if (c0 < n[0]) correct_row_across(q, phi, 1, c0, c1);
+    }
+    return;
+  }
   D* u = static_cast<D*>(q.vel[d]);
   const int ext = q.ext[d];
   int64_t s[3] = {n[0], n[1], n[2]};
@@ -94,29 +142,7 @@ __global__ void __launch_bounds__(PROJ_NT) proj_correct_kernel(ProjDev q, const 
       }
       continue;
     }
-    // faces across rows: the face index is c_d; phi rows of cells f and f - 1
-    const int64_t f = d == 0 ? c0 : c1;
-    const int64_t nd = n[d];
-    int64_t cc[2] = {c0, c1};
-    cc[d] = f < nd ? f : nd - 1;  // the cell above the face (below it for face n)
-    const D* hi = phi + cc[0] * cs[0] + cc[1] * cs[1];
-    const D* lo = nullptr;
-    double chi = 1.0, clo = -1.0;  // g = chi * phi[hi] + clo * phi[lo]
-    if (ext == 0) {
-      lo = f == 0 ? hi + (nd - 1) * cs[d] : hi - cs[d];
-    } else if (f == 0) {
-      if (!q.dlo[d]) continue;  // Neumann face: the velocity stays
-      chi = 2.0;
-    } else if (f == nd) {
-      if (!q.dhi[d]) continue;
-      chi = -2.0;
-    } else {
-      lo = hi - cs[d];
-    }
-    for (int64_t c2 = threadIdx.x; c2 < n[2]; c2 += PROJ_NT) {
-      const double g = chi * double(hi[c2]) + (lo ? clo * double(lo[c2]) : 0.0);
-      ur[c2] = D(double(ur[c2]) - cu * g);
-    }
+    correct_row_across(q, phi, d, c0, c1);
   }
 }
 
