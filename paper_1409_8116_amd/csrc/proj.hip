@@ -90,16 +90,55 @@ __device__ __forceinline__ void correct_row_across(const ProjDev& q, const D* ph
   }
 }
 
+// Row (c0, c1) of the face array of component 2 (faces along the row: phi
+// of the same cell row, cells f - 1 and f): u_2 -= adt grad_2 phi.
+template <typename D>
+__device__ __forceinline__ void correct_row_along(const ProjDev& q, const D* phi, int64_t c0, int64_t c1) {
+  const int64_t n1 = q.n[1], nn = q.n[2];
+  const int ext = q.ext[2];
+  const int64_t nf = nn + ext;
+  D* ur = static_cast<D*>(q.vel[2]) + (c0 * n1 + c1) * nf;
+  const D* pr = phi + (c0 * n1 + c1) * nn;
+  const double cu = q.adt * q.inv_h[2];
+  for (int64_t f = threadIdx.x; f < nf; f += PROJ_NT) {
+    double g;
+    if (ext == 0) g = double(pr[f]) - double(pr[f == 0 ? nn - 1 : f - 1]);
+    else if (f == 0) { if (!q.dlo[2]) continue; g = 2.0 * double(pr[0]); }
+    else if (f == nn) { if (!q.dhi[2]) continue; g = -2.0 * double(pr[nn - 1]); }
+    else g = double(pr[f]) - double(pr[f - 1]);
+    ur[f] = D(double(ur[f]) - cu * g);
+  }
+}
+
 // Component d (blockIdx.y < 3, when bit d of mask is set): u_d -= adt grad_d phi
 // on every face; blockIdx.y == 3 (when add_p): p += phi.  When components 0
-// and 1 are both corrected, the blocks of y = 0 take both over the union of
-// their face rows (the phi row of the cell above a face is then read once
-// for the two) and those of y = 1 stay idle.
+// and 1 are both corrected, the blocks of y = 0 do all of it over the union
+// of the face rows of 0 and 1 (a phi row is then read once for every update
+// that uses it: u, v, w and p) and the others stay idle.
 template <typename D>
 __global__ void __launch_bounds__(PROJ_NT) proj_correct_kernel(ProjDev q, const D* phi, int mask, int add_p) {
   const int d = int(blockIdx.y);
   const int64_t n[3] = {q.n[0], q.n[1], q.n[2]};
-  const int64_t cs[3] = {n[1] * n[2], n[2], 1};  // cell strides of phi
+  const bool both = (mask & 3) == 3 && q.vel[0] && q.vel[1];
+  if (both) {
+    if (d != 0) return;
+    const bool do_w = ((mask >> 2) & 1) && q.vel[2];
+    D* p = static_cast<D*>(q.p);
+    const int64_t r0 = n[0] + q.ext[0], r1 = n[1] + q.ext[1];
+    for (int64_t row = blockIdx.x; row < r0 * r1; row += gridDim.x) {
+      const int64_t c0 = row / r1, c1 = row - c0 * r1;
+      if (c1 < n[1]) correct_row_across(q, phi, 0, c0, c1);
+      if (c0 < n[0]) correct_row_across(q, phi, 1, c0, c1);
+      if (c0 < n[0] && c1 < n[1]) {
+        if (do_w) correct_row_along(q, phi, c0, c1);
+        if (add_p) {
+          const int64_t o = (c0 * n[1] + c1) * n[2];
+          for (int64_t c2 = threadIdx.x; c2 < n[2]; c2 += PROJ_NT) p[o + c2] = D(double(p[o + c2]) + double(phi[o + c2]));
+        }
+      }
+    }
+    return;
+  }
   if (d == 3) {
     if (!add_p) return;
     D* p = static_cast<D*>(q.p);
@@ -109,40 +148,12 @@ __global__ void __launch_bounds__(PROJ_NT) proj_correct_kernel(ProjDev q, const 
     return;
   }
   if (!((mask >> d) & 1) || !q.vel[d]) return;
-  const bool both = (mask & 3) == 3 && q.vel[0] && q.vel[1];
-  if (both && d < 2) {
-    if (d == 1) return;
-    const int64_t r0 = n[0] + q.ext[0], r1 = n[1] + q.ext[1];
-    for (int64_t row = blockIdx.x; row < r0 * r1; row += gridDim.x) {
-      const int64_t c0 = row / r1, c1 = row - c0 * r1;
-      if (c1 < n[1]) correct_row_across(q, phi, 0, c0, c1);
-      if (c0 < n[0]) correct_row_across(q, phi, 1, c0, c1);
-    }
-    return;
-  }
-  D* u = static_cast<D*>(q.vel[d]);
-  const int ext = q.ext[d];
-  int64_t s[3] = {n[0], n[1], n[2]};
-  s[d] += ext;
-  const double cu = q.adt * q.inv_h[d];
-  for (int64_t row = blockIdx.x; row < s[0] * s[1]; row += gridDim.x) {
-    const int64_t c0 = row / s[1], c1 = row - c0 * s[1];
-    D* ur = u + row * s[2];
-    if (d == 2) {
-      // faces along the row: phi of the same row, cells f - 1 and f
-      const D* pr = phi + c0 * cs[0] + c1 * cs[1];
-      const int64_t nn = n[2];
-      for (int64_t f = threadIdx.x; f < s[2]; f += PROJ_NT) {
-        double g;
-        if (ext == 0) g = double(pr[f]) - double(pr[f == 0 ? nn - 1 : f - 1]);
-        else if (f == 0) { if (!q.dlo[2]) continue; g = 2.0 * double(pr[0]); }
-        else if (f == nn) { if (!q.dhi[2]) continue; g = -2.0 * double(pr[nn - 1]); }
-        else g = double(pr[f]) - double(pr[f - 1]);
-        ur[f] = D(double(ur[f]) - cu * g);
-      }
-      continue;
-    }
-    correct_row_across(q, phi, d, c0, c1);
+  // rows of component d's face array (axis d may have one more face)
+  const int64_t s0 = n[0] + (d == 0 ? q.ext[0] : 0), s1 = n[1] + (d == 1 ? q.ext[1] : 0);
+  for (int64_t row = blockIdx.x; row < s0 * s1; row += gridDim.x) {
+    const int64_t c0 = row / s1, c1 = row - c0 * s1;
+    if (d == 2) correct_row_along(q, phi, c0, c1);
+    else correct_row_across(q, phi, d, c0, c1);
   }
 }
 
